@@ -1,0 +1,267 @@
+"""Seeded synthetic workloads: solid masks, initial densities and run settings.
+
+This module holds no arithmetic of the lattice Boltzmann method; it only
+draws geometries and initial conditions, so both the GPU library and the CPU
+oracle can be fed the same inputs.  Random draws use
+``numpy.random.default_rng(seed)`` (PCG64) in the order written here.
+
+Initial densities follow the paper's main/dissolved notion (Sec. 2.1,
+Fig. 1): the dominant component at a node starts at ``RHO_MAJOR`` and the
+other at ``RHO_MINOR``, mirrored between the two components.
+
+Workloads (sizes from the run configurations):
+  flat_drop       100x50 channel, droplet cap on the bottom wall      (flat contact angle)
+  cylinder_drop   400x400 periodic box, droplet on a cylinder          (curved contact angle)
+  porous          2048x1024 channel of random disks, displacement      (precision study)
+  calibration     512 square runs, flat or cylinder walls              (batching)
+  constrictions   16384x2048 channel with 64 square constrictions     (throughput)
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+PERIODIC_X = 1
+PERIODIC_Y = 2
+
+RHO_MAJOR = 1.0
+RHO_MINOR = 0.03
+
+WALL_FLAT = 0
+WALL_CYLINDER = 1
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    flags: int
+    solid: np.ndarray            # uint8 [ny, nx], 1 = solid
+    rho1: np.ndarray             # float64 [ny, nx]
+    rho2: np.ndarray             # float64 [ny, nx]
+    G_c: float = 0.9
+    G_ads: float = 0.0
+    tau: float = 1.0
+    accel: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
+    steps: int = 1000
+    wall_kind: Optional[int] = None
+    wall: Optional[Tuple[float, float, float]] = None
+
+    @property
+    def n_nodes(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def n_fluid(self) -> int:
+        return int(self.n_nodes - int(self.solid.sum()))
+
+    def mask_sha256(self) -> str:
+        return hashlib.sha256(np.ascontiguousarray(self.solid, dtype=np.uint8).tobytes()).hexdigest()
+
+
+def _grid(nx: int, ny: int):
+    y, x = np.mgrid[0:ny, 0:nx]
+    return x.astype(np.float64), y.astype(np.float64)
+
+
+def _two_phase(inside: np.ndarray, solid: np.ndarray):
+    """Component 1 dominant where ``inside``; mirrored for component 2."""
+    rho1 = np.where(inside, RHO_MAJOR, RHO_MINOR).astype(np.float64)
+    rho2 = np.where(inside, RHO_MINOR, RHO_MAJOR).astype(np.float64)
+    rho1[solid != 0] = 0.0
+    rho2[solid != 0] = 0.0
+    return rho1, rho2
+
+
+def flat_drop(nx: int = 100, ny: int = 50, radius: float = 20.0, G_ads: float = 0.2,
+              G_c: float = 0.9, tau: float = 1.0, steps: int = 5000) -> Workload:
+    """Semicircular droplet centred on a flat bottom wall.
+
+    Solid rows y = 0 and y = ny-1, periodic in x; the droplet is
+    (x - nx/2)^2 + (y - 0.5)^2 < r^2 (strict).  Flat-wall angle is read with
+    the wall line at y = 0.5 (halfway bounce-back)."""
+    x, y = _grid(nx, ny)
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[ny - 1, :] = 1
+    inside = (x - nx / 2.0) ** 2 + (y - 0.5) ** 2 < radius * radius
+    rho1, rho2 = _two_phase(inside, solid)
+    return Workload("flat_drop", nx, ny, PERIODIC_X, solid, rho1, rho2, G_c=G_c, G_ads=G_ads,
+                    tau=tau, steps=steps, wall_kind=WALL_FLAT, wall=(0.5, 0.0, 0.0))
+
+
+def cylinder_drop(G_ads: float = 0.0, nx: int = 400, ny: int = 400, R: float = 60.0,
+                  centre=(200.0, 150.0), r_drop: float = 50.0, drop_centre=(200.0, 240.0),
+                  G_c: float = 0.9, tau: float = 1.0, steps: int = 20000) -> Workload:
+    """Droplet on a staircase-voxelised cylinder in a fully periodic box.
+
+    Solid where (x-cx)^2 + (y-cy)^2 <= R^2; droplet (strict <) centred at
+    ``drop_centre``.  The wall surface for the angle is R + 0.5."""
+    x, y = _grid(nx, ny)
+    solid = (((x - centre[0]) ** 2 + (y - centre[1]) ** 2) <= R * R).astype(np.uint8)
+    inside = (x - drop_centre[0]) ** 2 + (y - drop_centre[1]) ** 2 < r_drop * r_drop
+    rho1, rho2 = _two_phase(inside, solid)
+    return Workload("cylinder_drop", nx, ny, PERIODIC_X | PERIODIC_Y, solid, rho1, rho2, G_c=G_c,
+                    G_ads=G_ads, tau=tau, steps=steps, wall_kind=WALL_CYLINDER,
+                    wall=(centre[0], centre[1], R + 0.5))
+
+
+CYLINDER_SWEEP = [-0.3, -0.2, -0.1, 0.0, 0.1, 0.2, 0.3]
+
+
+def porous(nx: int = 2048, ny: int = 1024, seed: int = 2505, solid_fraction: float = 0.30,
+           inlet: int = 64, window_x0: int = 96, steps: int = 50000,
+           max_attempts: int = 2_000_000) -> Workload:
+    """Random non-overlapping disks in a walled channel (porosity ~0.7).
+
+    Random sequential addition: per attempt draw r ~ U[8, 24), then the
+    centre x ~ U[x0 + r, nx - r - 2), y ~ U[3 + r, ny - 3 - r); accept when the
+    gap to every placed disk is at least 2.  Stop once the disks cover
+    ``solid_fraction`` of the interior window x >= x0.  Component 1 fills the
+    fluid for x < ``inlet`` and is driven by the body acceleration 1e-6."""
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[ny - 1, :] = 1
+    window_area = (nx - window_x0) * (ny - 2)
+    disks: List[Tuple[float, float, float]] = []
+    covered = 0
+    attempts = 0
+    while covered < solid_fraction * window_area and attempts < max_attempts:
+        attempts += 1
+        r = rng.uniform(8.0, 24.0)
+        cx = rng.uniform(window_x0 + r, nx - r - 2.0)
+        cy = rng.uniform(3.0 + r, ny - 3.0 - r)
+        ok = True
+        for (qx, qy, qr) in disks:
+            if (cx - qx) ** 2 + (cy - qy) ** 2 < (r + qr + 2.0) ** 2:
+                ok = False
+                break
+        if not ok:
+            continue
+        disks.append((cx, cy, r))
+        x0, x1 = int(np.floor(cx - r)), int(np.ceil(cx + r)) + 1
+        y0, y1 = int(np.floor(cy - r)), int(np.ceil(cy + r)) + 1
+        yy, xx = np.mgrid[y0:y1, x0:x1]
+        disk = ((xx - cx) ** 2 + (yy - cy) ** 2) <= r * r
+        solid[y0:y1, x0:x1] |= disk.astype(np.uint8)
+        covered += int(disk.sum())
+    x, _ = _grid(nx, ny)
+    rho1, rho2 = _two_phase(x < inlet, solid)
+    wl = Workload("porous", nx, ny, PERIODIC_X, solid, rho1, rho2, G_c=0.9, G_ads=0.0, tau=1.0,
+                  accel=(1e-6, 0.0, 0.0, 0.0), steps=steps)
+    wl.disks = disks  # type: ignore[attr-defined]
+    return wl
+
+
+def calibration_runs(seed: int = 22256, nruns: int = 512, steps: int = 10000) -> List[Workload]:
+    """Contact-angle calibration batch of uneven square lattices.
+
+    Per run draw: side from {128, 192, 256, 384, 512}; wall flat or cylinder
+    (Bernoulli 0.5); G_ads ~ U[-0.35, 0.35]; tau ~ U[0.7, 1.2].  Droplet radius
+    0.2 side.  Flat: walls at rows 0 and side-1, droplet centre (side/2, 0.5).
+    Cylinder: periodic, R = 0.15 side at (side/2, 0.375 side), droplet centre
+    (side/2, 0.675 side)."""
+    rng = np.random.default_rng(seed)
+    sides = [128, 192, 256, 384, 512]
+    runs = []
+    for _ in range(nruns):
+        side = int(sides[int(rng.integers(0, len(sides)))])
+        cyl = bool(rng.random() < 0.5)
+        G_ads = float(rng.uniform(-0.35, 0.35))
+        tau = float(rng.uniform(0.7, 1.2))
+        if cyl:
+            w = cylinder_drop(G_ads=G_ads, nx=side, ny=side, R=0.15 * side,
+                              centre=(side / 2.0, 0.375 * side), r_drop=0.2 * side,
+                              drop_centre=(side / 2.0, 0.675 * side), tau=tau, steps=steps)
+        else:
+            w = flat_drop(nx=side, ny=side, radius=0.2 * side, G_ads=G_ads, tau=tau, steps=steps)
+        w.name = "calibration"
+        runs.append(w)
+    return runs
+
+
+def constrictions(nx: int = 16384, ny: int = 2048, seed: int = 355, n_squares: int = 64,
+                  side: int = 128, steps: int = 100000) -> Workload:
+    """Long walled microchannel with a seeded row of square constrictions.
+
+    Square j starts at x0 = (nx / n_squares) j + U_int[32, 96] and is attached
+    to the bottom wall (rows [1, 1+side)) or the top wall (rows
+    [ny-1-side, ny-1)) by a fair coin, drawn in that order.  Component 1
+    fills y < ny/2, component 2 the rest; both are driven along x."""
+    rng = np.random.default_rng(seed)
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[ny - 1, :] = 1
+    pitch = nx // n_squares
+    for j in range(n_squares):
+        x0 = pitch * j + int(rng.integers(32, 97))
+        top = bool(rng.random() < 0.5)
+        y0 = ny - 1 - side if top else 1
+        solid[y0:y0 + side, x0:x0 + side] = 1
+    _, y = _grid(nx, ny)
+    rho1, rho2 = _two_phase(y < ny / 2.0, solid)
+    return Workload("constrictions", nx, ny, PERIODIC_X, solid, rho1, rho2, G_c=0.9, G_ads=0.15,
+                    tau=1.0, accel=(2e-6, 0.0, 2e-6, 0.0), steps=steps)
+
+
+def random_small(seed: int, nx: int = 24, ny: int = 18, flags: int = PERIODIC_X | PERIODIC_Y,
+                 n_blobs: int = 3, walls: bool = False, drop: bool = True) -> Workload:
+    """Small random geometry for parity cases: a few solid blobs (discs and
+    rectangles at least 2 nodes thick) and a random droplet."""
+    rng = np.random.default_rng(seed)
+    x, y = _grid(nx, ny)
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    if walls:
+        solid[0, :] = 1
+        solid[ny - 1, :] = 1
+    for _ in range(n_blobs):
+        kind = int(rng.integers(0, 2))
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        if kind == 0:
+            r = rng.uniform(1.5, 4.0)
+            dx = np.minimum(np.abs(x - cx), nx - np.abs(x - cx)) if flags & PERIODIC_X else x - cx
+            dy = np.minimum(np.abs(y - cy), ny - np.abs(y - cy)) if flags & PERIODIC_Y else y - cy
+            solid |= ((dx ** 2 + dy ** 2) <= r * r).astype(np.uint8)
+        else:
+            w, h = int(rng.integers(2, 6)), int(rng.integers(2, 6))
+            x0, y0 = int(cx), int(cy)
+            for j in range(h):
+                for i in range(w):
+                    xx, yy = x0 + i, y0 + j
+                    if flags & PERIODIC_X:
+                        xx %= nx
+                    if flags & PERIODIC_Y:
+                        yy %= ny
+                    if 0 <= xx < nx and 0 <= yy < ny:
+                        solid[yy, xx] = 1
+    if drop:
+        dcx, dcy, dr = rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(3.0, min(nx, ny) / 3.0)
+        inside = (x - dcx) ** 2 + (y - dcy) ** 2 < dr * dr
+    else:
+        inside = np.zeros((ny, nx), dtype=bool)
+    rho1, rho2 = _two_phase(inside, solid)
+    # a small seeded perturbation so that no two nodes start identical
+    pert = rng.uniform(-0.01, 0.01, size=(2, ny, nx))
+    rho1 = np.where(solid != 0, 0.0, rho1 + pert[0] * rho1)
+    rho2 = np.where(solid != 0, 0.0, rho2 + pert[1] * rho2)
+    return Workload("random_small", nx, ny, flags, solid, rho1, rho2, G_c=0.9,
+                    G_ads=float(rng.uniform(-0.3, 0.3)), tau=float(rng.uniform(0.7, 1.3)),
+                    accel=(float(rng.uniform(-1e-4, 1e-4)), float(rng.uniform(-1e-4, 1e-4)),
+                           float(rng.uniform(-1e-4, 1e-4)), float(rng.uniform(-1e-4, 1e-4))),
+                    steps=100)
+
+
+def random_populations(seed: int, wl: Workload, amplitude: float = 0.2) -> np.ndarray:
+    """Seeded non-equilibrium population set [2, 9, ny, nx] around
+    w_i-free uniform values: f_i = rho_k/9 * (1 + a U[-1, 1)).  Solid entries
+    are zero.  Used to start parity runs far from equilibrium."""
+    rng = np.random.default_rng(seed)
+    base = np.stack([wl.rho1, wl.rho2])[:, None, :, :] / 9.0
+    f = base * (1.0 + amplitude * rng.uniform(-1.0, 1.0, size=(2, 9, wl.ny, wl.nx)))
+    f[:, :, wl.solid != 0] = 0.0
+    return f

@@ -1,0 +1,26 @@
+"""Shared pytest configuration.
+
+Markers
+  gpu   needs an MI355X (gfx950) and the built HIP library; parity and
+        device-side checks.  Everything else runs on the CPU.
+"""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long CPU run (oracle physics), skipped with -m 'not slow'")
+
+
+@pytest.fixture(scope="session")
+def oracle_mod():
+    import oracle
+    oracle.build(force=False)
+    return oracle
