@@ -1,0 +1,229 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) two-component pseudopotential
+ * lattice Boltzmann hot path.
+ *
+ * Method: Chen, Wang, Tao, Yang, Chen, "Improvement of Solid-Fluid
+ * Interaction Scheme in Lattice Boltzmann Immiscible Pseudopotential Models"
+ * (arXiv 2505.22256):
+ *   - two D2Q9 population sets, BGK collision with Guo forcing (Sec. 2.1-2.2,
+ *     Eq. 1-7), one relaxation time for both components;
+ *   - fluid-fluid cohesion with psi = rho on the eighth-order-isotropic (E8)
+ *     24-position stencil (Eq. 8, Sec. 2.4);
+ *   - second-layer stencil data at walls copied from the first layer
+ *     (Sec. 2.4, Table 1);
+ *   - Martys-Chen adhesion (Eq. 9) with the local, effective-density
+ *     dependent parameter of component 1 (Eq. 10-12);
+ *   - halfway bounce-back at solid nodes and at non-periodic domain edges
+ *     (Sec. 3.1, 3.2, 3.5).
+ *
+ * Conventions shared by every entry point
+ *   - Lattice nx x ny, node id = y*nx + x (x fastest).  Host arrays of one
+ *     value per node are [ny][nx]; population arrays are [2][9][ny][nx]
+ *     (component, D2Q9 direction, node) with the directions
+ *     e_0 = (0,0), e_1..e_8 = (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ *   - All host pointers are owned by the caller; the library copies in or
+ *     out and keeps no host pointer after the call returns.  The library owns
+ *     all device memory of a context.
+ *   - Every int-returning call returns LBM_OK (0) or a negative LBM_E* code
+ *     and never aborts; lbm_last_error() gives a message.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Work is enqueued on the context's HIP stream (lbm_set_stream); calls
+ *     that return host data synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* bad argument or parameter                      */
+    LBM_ESTATE = -2,    /* call out of order (e.g. step before init)       */
+    LBM_ENOMEM = -3,    /* host or device allocation failed                */
+    LBM_EDEVICE = -4,   /* HIP runtime error, or no usable gfx950 device   */
+    LBM_EUNSTABLE = -5, /* non-finite state, or the contact angle failed   */
+    LBM_EIO = -6        /* checkpoint file error                           */
+};
+
+/* Population storage.  F64 stores f and computes in FP64.  F32, F16 and
+ * BF16 store the deviation g_i = f_i - w_i rho0_k (rho0_k = mean initial
+ * density of component k over fluid nodes), rounded to nearest even, and
+ * compute in FP32. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
+
+/* Context flags.  PERIODIC_* wrap an axis; along a non-periodic axis the
+ * outside counts as solid.  The others select alternative readings of
+ * points the paper leaves open:
+ *   SCHEME_ORIGINAL  constant G_w1 for component 1 (Eq. 9, Sec. 2.3.1);
+ *   E8_COPY_OFF      unavailable second-layer positions read 0 (no Table 1 copy);
+ *   WALLPSI_SELF     unavailable first-layer positions read psi(x) instead of 0;
+ *   VEL_LITERAL      u^eq = sum_k j_k / sum_k rho_k (Eq. 4-5 without the
+ *                    half-force shift of Guo's scheme);
+ *   FORCE_DENSITY    body force g_k per unit volume instead of rho_k g_k. */
+enum {
+    LBM_PERIODIC_X = 1,
+    LBM_PERIODIC_Y = 2,
+    LBM_SCHEME_ORIGINAL = 4,
+    LBM_E8_COPY_OFF = 8,
+    LBM_WALLPSI_SELF = 16,
+    LBM_VEL_LITERAL = 32,
+    LBM_FORCE_DENSITY = 64
+};
+
+/* Contact-angle wall kinds for lbm_contact_angle. */
+enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
+
+/* Create a context on the current HIP device.  nx, ny >= 5; storage one of
+ * LBM_F64..LBM_BF16; flags a combination of LBM_PERIODIC_X..LBM_FORCE_DENSITY.
+ * Allocates two population buffers of 18*nx*ny elements (ping-pong).
+ * Errors: EINVAL (sizes, storage, flags), ENOMEM, EDEVICE (no gfx950 GPU). */
+int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags);
+
+/* Solid mask, ny*nx bytes, 0 = fluid, non-zero = solid (the switch s(x) of
+ * Eq. 9).  Copied.  Invalidates the populations (init again). */
+int lbm_set_geometry(lbm_ctx *c, const uint8_t *solid);
+
+/* Physical parameters: cohesion G_c (Eq. 8), adhesion G_ads and relaxation
+ * time tau (Eq. 2).  Adhesion mapping: G_w2 = G_c, G_w1 = G_c + 2 G_ads,
+ * delta = 0.8 (Sec. 2.3.2: G_w2 = G12, lambda = G_w1/G_w2 = 1 + 2 G_ads/G_c).
+ * EINVAL if tau <= 0.5, if a value is non-finite, or, for the improved
+ * scheme, if lambda <= 0 or G_w1 + G_w2 == 0. */
+int lbm_set_params(lbm_ctx *c, double G_c, double G_ads, double tau);
+
+/* Paper-native adhesion parameters of Eq. 9-12 (after lbm_set_params).
+ * EINVAL if delta <= 0 or, for the improved scheme, G_w1 + G_w2 == 0. */
+int lbm_set_adhesion(lbm_ctx *c, double G_w1, double G_w2, double delta);
+
+/* Body acceleration g_k of each component (force rho_k g_k, Sec. 3.1). */
+int lbm_set_body_accel(lbm_ctx *c, double g1x, double g1y, double g2x, double g2y);
+
+/* Initial densities (ny*nx each, FP64): f_i = w_i rho_k, u = 0, t = 0.
+ * Solid entries are ignored.  EINVAL on a non-finite fluid density. */
+int lbm_init_fields(lbm_ctx *c, const double *rho1, const double *rho2);
+
+/* Pre-collision populations f(x, t) as [2][9][ny][nx] FP64; solid entries
+ * ignored on input, returned as 0.  set_populations resets t to 0. */
+int lbm_set_populations(lbm_ctx *c, const double *f);
+int lbm_get_populations(lbm_ctx *c, double *f);
+
+/* Pre-collision populations f(x, t) of the w x h window whose lower-left
+ * node is (x0, y0), as [2][9][h][w] FP64 (solid -> 0).  The window wraps
+ * along periodic axes; EINVAL if it leaves a non-periodic domain or
+ * w, h < 1.  Synchronous. */
+int lbm_get_populations_window(lbm_ctx *c, int x0, int y0, int w, int h, double *f);
+
+/* Advance n >= 0 time steps (collide, then stream).  Asynchronous: the
+ * kernels are enqueued on the context stream.  ESTATE before geometry,
+ * parameters and initial fields. */
+int lbm_step(lbm_ctx *c, int n);
+
+/* Wait for all work of the context; EDEVICE if a kernel failed. */
+int lbm_synchronize(lbm_ctx *c);
+
+/* Number of steps taken since the last initialisation. */
+long lbm_time(const lbm_ctx *c);
+
+/* Densities rho_k and the common velocity u^eq (Eq. 3-5 with the Guo
+ * half-force shift) at the current time, ny*nx FP64 each; NULL skips an
+ * output; solid nodes give 0.  Synchronous. */
+int lbm_get_fields(lbm_ctx *c, double *rho1, double *rho2, double *ux, double *uy);
+
+/* Whole-lattice diagnostics at the current time, FP64 with a deterministic
+ * compensated two-pass sum: out = {M1, M2, Px, Py, max|u|, min rho1,
+ * max rho1, number of fluid nodes with a non-finite rho or u}, where
+ * M_k = sum rho_k and P = sum (rho_1 + rho_2) u^eq over fluid nodes. */
+int lbm_reduce(lbm_ctx *c, double out[8]);
+
+/* Static contact angle (degrees, measured through component 1).  Interface
+ * points where rho^e = (rho1 - rho2)/(rho1 + rho2) (Eq. 10) changes sign
+ * along x- and y-links between fluid nodes, by linear interpolation; points
+ * closer than 3 lattice units to the wall are dropped; algebraic circle fit
+ * refined by Gauss-Newton, in FP64 on the device.
+ *   wall_kind LBM_WALL_FLAT:     wall[0] = wall line y_w (drop above it);
+ *   wall_kind LBM_WALL_CYLINDER: wall[0..1] = centre, wall[2] = surface radius.
+ * EUNSTABLE if fewer than 3 points remain or the fit fails. */
+int lbm_contact_angle(lbm_ctx *c, int wall_kind, const double wall[3], double *theta_deg);
+
+/* Tables the step kernel derives from the geometry, for checking:
+ *   link[ny*nx]: bit i-1 set when the pull source x - e_i of fluid node x is
+ *     unavailable (bounce-back); 0 on solid nodes;
+ *   nw_list[n_nw]: fluid nodes with an unavailable E8 stencil position,
+ *     ascending;
+ *   nw_src[24*n_nw]: per listed node and stencil position n = 1..24, the node
+ *     whose psi is used after the wall rules, or -1 for zero.  Stencil order:
+ *     1-8 the D2Q9 links e_1..e_8, 9-16 twice e_1..e_8, then (2,1) (-1,2)
+ *     (-2,-1) (1,-2) (1,2) (-2,1) (-1,-2) (2,-1).
+ * Pass nw_list = NULL to query n_nw only.  Synchronous. */
+int lbm_get_tables(lbm_ctx *c, uint8_t *link, int32_t *nw_list, int32_t *nw_src, int *n_nw);
+
+/* Use an existing HIP stream (hipStream_t, e.g. a torch stream handle);
+ * NULL selects the library's own stream. */
+int lbm_set_stream(lbm_ctx *c, void *hip_stream);
+
+/* Tile shape of the step kernel: block in {64, 128, 256} threads (strip
+ * width block - 4 columns) and target rows per workgroup segment (>= 1).
+ * lbm_autotune times the candidates for `steps` steps each on the current
+ * state (restoring it afterwards) and keeps the fastest. */
+int lbm_set_tile(lbm_ctx *c, int block, int seg_rows);
+int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows);
+int lbm_autotune(lbm_ctx *c, int steps);
+
+/* Checkpoint: populations, time, parameters.  EIO on file errors; load
+ * requires a context of the same size, storage and flags. */
+int lbm_save(lbm_ctx *c, const char *path);
+int lbm_load(lbm_ctx *c, const char *path);
+
+/* Number of fluid nodes (after set_geometry), and the algorithmic bytes per
+ * fluid-node update of the step for this storage: 2 components x 9
+ * populations x (read + write) + 1 byte of geometry. */
+long lbm_fluid_nodes(const lbm_ctx *c);
+int lbm_bytes_per_update(const lbm_ctx *c);
+
+const char *lbm_last_error(const lbm_ctx *c);
+void lbm_destroy(lbm_ctx *c);
+
+/* ------------------------------------------------------------------ */
+/* Batching: many independent runs in one launch per time step          */
+/* ------------------------------------------------------------------ */
+
+/* One run of a batch.  Arrays are ny*nx and copied at creation.  accel may
+ * be NULL (no body force). */
+typedef struct {
+    int nx, ny;
+    unsigned flags;
+    double G_c, G_ads, tau;
+    int wall_kind;
+    double wall[3];
+    const uint8_t *solid;
+    const double *rho1, *rho2;
+    const double *accel; /* g1x, g1y, g2x, g2y or NULL */
+} lbm_run_desc;
+
+/* Create a batch of nruns runs with one storage type.  Every run is advanced
+ * by one kernel launch per time step over a (run, strip, segment) work list;
+ * with `use_graph` non-zero, lbm_batch_step replays a captured HIP graph.
+ * Each run's result is bitwise that of a single context with the same
+ * inputs and tile shape. */
+int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int storage);
+int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows);
+int lbm_batch_step(lbm_batch *b, int n);
+int lbm_batch_use_graph(lbm_batch *b, int use_graph, int steps_per_graph);
+int lbm_batch_get_fields(lbm_batch *b, int run, double *rho1, double *rho2, double *ux, double *uy);
+int lbm_batch_contact_angles(lbm_batch *b, double *theta_deg);
+int lbm_batch_set_stream(lbm_batch *b, void *hip_stream);
+long lbm_batch_fluid_nodes(const lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+void lbm_batch_destroy(lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,793 @@
+// Host side of the C ABI declared in include/lbm.h: contexts, parameter
+// mapping, launches, diagnostics, tables, checkpoints and the tile tuner.
+#include "lbm.h"
+#include "lbm_kernels.hpp"
+#include "lbm_params.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbm;
+
+struct lbm_ctx {
+    int nx = 0, ny = 0, storage = 0;
+    unsigned flags = 0;
+    long long N = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;  // buffer holding the post-collision set of the previous step
+    uint8_t *d_solid = nullptr;
+    double *d_tmp = nullptr;  // staging: fields (4N doubles) or populations (18N)
+    size_t tmp_bytes = 0;
+    double *d_partials = nullptr;
+    size_t partials_cap = 0;
+    double *d_out = nullptr;  // 8 reduction results + 6 contact-angle results
+    std::vector<uint8_t> solid;
+    long long n_fluid = 0;
+    double Gc = 0, Gw1 = 0, Gw2 = 0, delta = 0.8, tau = 1.0;
+    double acc[2][2] = {{0, 0}, {0, 0}};
+    double rho0[2] = {0, 0};
+    bool have_geom = false, have_params = false, have_fields = false;
+    long t = 0;
+    int block = 256, seg_rows = 64;
+    std::string err;
+};
+
+namespace lbm_host {
+
+int set_err(lbm_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return lbm_host::set_err((c), LBM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t elem_size(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F32 ? 4 : 2; }
+
+bool valid_block(int b) { return b == 64 || b == 128 || b == 256; }
+
+int ensure_tmp(lbm_ctx *c, size_t bytes)
+{
+    if (c->tmp_bytes >= bytes) return LBM_OK;
+    if (c->d_tmp) (void)hipFree(c->d_tmp);
+    c->d_tmp = nullptr;
+    c->tmp_bytes = 0;
+    if (hipMalloc(&c->d_tmp, bytes) != hipSuccess)
+        return set_err(c, LBM_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    c->tmp_bytes = bytes;
+    return LBM_OK;
+}
+
+int ensure_partials(lbm_ctx *c, size_t nparts)
+{
+    if (c->partials_cap >= nparts) return LBM_OK;
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    c->d_partials = nullptr;
+    c->partials_cap = 0;
+    if (hipMalloc(&c->d_partials, nparts * 8 * sizeof(double)) != hipSuccess)
+        return set_err(c, LBM_ENOMEM, "partials allocation failed");
+    c->partials_cap = nparts;
+    return LBM_OK;
+}
+
+template <class C>
+KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int seg_rows)
+{
+    KParams<C> p;
+    std::memset(&p, 0, sizeof p);
+    p.A = A;
+    p.B = B;
+    p.nx = c->nx;
+    p.ny = c->ny;
+    p.flags = c->flags;
+    tile_counts(block, seg_rows, c->nx, c->ny, &p.n_strips, &p.n_segs);
+    p.item0 = 0;
+    p.N = c->N;
+    fill_physics<C>(p, c->flags, c->Gc, c->Gw1, c->Gw2, c->delta, c->tau, c->acc, c->rho0, c->storage != LBM_F64);
+    return p;
+}
+
+int grid_of(int strips, int segs) { return ((strips * segs + 7) / 8) * 8; }
+
+template <int S, int BLOCK, int MODE>
+hipError_t launch_step_t(const KParams<typename Traits<S>::C> &p, hipStream_t st)
+{
+    const int items = p.n_strips * p.n_segs;
+    const int per_xcd = (items + 7) / 8;
+    hipLaunchKernelGGL((k_step<S, BLOCK, MODE>), dim3(per_xcd * 8), dim3(BLOCK), 0, st, p, per_xcd);
+    return hipGetLastError();
+}
+
+template <int S, int MODE>
+hipError_t launch_step_b(const KParams<typename Traits<S>::C> &p, int block, hipStream_t st)
+{
+    switch (block) {
+    case 64: return launch_step_t<S, 64, MODE>(p, st);
+    case 128: return launch_step_t<S, 128, MODE>(p, st);
+    default: return launch_step_t<S, 256, MODE>(p, st);
+    }
+}
+
+// Kinds of pass over the lattice.
+enum Pass { P_STEP, P_STEP_REDUCE, P_FIELDS_REDUCE, P_TABLES };
+
+// Launch one pass reading buf[cur].  P_STEP* write buf[cur^1] (the caller
+// flips cur).  Returns the number of partial records in *nparts.
+template <int S>
+int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts)
+{
+    using C = typename Traits<S>::C;
+    const int block = (pass == P_STEP || pass == P_STEP_REDUCE) ? c->block : 256;
+    KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, c->seg_rows);
+    const int grid = grid_of(p.n_strips, p.n_segs);
+    if (nparts) *nparts = grid;
+    if (pass == P_STEP_REDUCE || pass == P_FIELDS_REDUCE) {
+        int rc = ensure_partials(c, (size_t)grid);
+        if (rc) return rc;
+        p.partials = c->d_partials;
+    }
+    if (fields) {
+        p.out_rho1 = fields;
+        p.out_rho2 = fields + c->N;
+        p.out_ux = fields + 2 * c->N;
+        p.out_uy = fields + 3 * c->N;
+    }
+    p.tab_link = link;
+    p.tab_nw = nw;
+    p.tab_src = src;
+    hipError_t e = hipSuccess;
+    switch (pass) {
+    case P_STEP: e = launch_step_b<S, M_STORE>(p, block, c->stream); break;
+    case P_STEP_REDUCE: e = launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream); break;
+    case P_FIELDS_REDUCE: e = launch_step_t<S, 256, M_FIELDS | M_REDUCE>(p, c->stream); break;
+    case P_TABLES: e = launch_step_t<S, 256, M_TABLES>(p, c->stream); break;
+    }
+    if (e != hipSuccess) return set_err(c, LBM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int run_pass(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts)
+{
+    switch (c->storage) {
+    case LBM_F64: return run_pass_t<ST_F64>(c, pass, fields, link, nw, src, nparts);
+    case LBM_F32: return run_pass_t<ST_F32>(c, pass, fields, link, nw, src, nparts);
+    case LBM_F16: return run_pass_t<ST_F16>(c, pass, fields, link, nw, src, nparts);
+    default: return run_pass_t<ST_BF16>(c, pass, fields, link, nw, src, nparts);
+    }
+}
+
+// Write the post-collision set whose streaming gives f(t) (from `fsrc`
+// [2][9][N] FP64, or from `rho` [2][N] at rest) into buf[cur].
+template <int S>
+int inverse_stream_t(lbm_ctx *c, const double *fsrc, const double *rho)
+{
+    using C = typename Traits<S>::C;
+    KParams<C> p = make_params<C>(c, nullptr, c->buf[c->cur], 256, 64);
+    const long long blocks = (c->N + 255) / 256;
+    hipLaunchKernelGGL((k_inverse_stream<S>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, c->d_solid, fsrc, rho);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+int inverse_stream(lbm_ctx *c, const double *fsrc, const double *rho)
+{
+    switch (c->storage) {
+    case LBM_F64: return inverse_stream_t<ST_F64>(c, fsrc, rho);
+    case LBM_F32: return inverse_stream_t<ST_F32>(c, fsrc, rho);
+    case LBM_F16: return inverse_stream_t<ST_F16>(c, fsrc, rho);
+    default: return inverse_stream_t<ST_BF16>(c, fsrc, rho);
+    }
+}
+
+template <int S>
+int pull_populations_t(lbm_ctx *c, double *out)
+{
+    using C = typename Traits<S>::C;
+    KParams<C> p = make_params<C>(c, c->buf[c->cur], nullptr, 256, 64);
+    const long long blocks = (c->N + 255) / 256;
+    hipLaunchKernelGGL((k_pull_populations<S>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, out);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+int pull_populations(lbm_ctx *c, double *out)
+{
+    switch (c->storage) {
+    case LBM_F64: return pull_populations_t<ST_F64>(c, out);
+    case LBM_F32: return pull_populations_t<ST_F32>(c, out);
+    case LBM_F16: return pull_populations_t<ST_F16>(c, out);
+    default: return pull_populations_t<ST_BF16>(c, out);
+    }
+}
+
+template <int S>
+int pull_window_t(lbm_ctx *c, int x0, int y0, int w, int h, double *out)
+{
+    using C = typename Traits<S>::C;
+    KParams<C> p = make_params<C>(c, c->buf[c->cur], nullptr, 256, 64);
+    const long long blocks = ((long long)w * h + 255) / 256;
+    hipLaunchKernelGGL((k_pull_window<S>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, x0, y0, w, h, out);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+int pull_window(lbm_ctx *c, int x0, int y0, int w, int h, double *out)
+{
+    switch (c->storage) {
+    case LBM_F64: return pull_window_t<ST_F64>(c, x0, y0, w, h, out);
+    case LBM_F32: return pull_window_t<ST_F32>(c, x0, y0, w, h, out);
+    case LBM_F16: return pull_window_t<ST_F16>(c, x0, y0, w, h, out);
+    default: return pull_window_t<ST_BF16>(c, x0, y0, w, h, out);
+    }
+}
+
+int ready(lbm_ctx *c)
+{
+    if (!c) return LBM_EINVAL;
+    if (!c->have_geom) return set_err(c, LBM_ESTATE, "set_geometry first");
+    if (!c->have_params) return set_err(c, LBM_ESTATE, "set_params first");
+    if (!c->have_fields) return set_err(c, LBM_ESTATE, "init_fields or set_populations first");
+    return LBM_OK;
+}
+
+int check_adhesion(lbm_ctx *c, double Gw1, double Gw2, double delta)
+{
+    if (!(delta > 0.0) || !std::isfinite(delta)) return set_err(c, LBM_EINVAL, "delta must be > 0");
+    if (!std::isfinite(Gw1) || !std::isfinite(Gw2)) return set_err(c, LBM_EINVAL, "non-finite adhesion parameter");
+    if (!(c->flags & LBM_SCHEME_ORIGINAL) && Gw1 + Gw2 == 0.0)
+        return set_err(c, LBM_EINVAL, "improved scheme needs G_w1 + G_w2 != 0");
+    return LBM_OK;
+}
+
+// Run the fields+diagnostics pass into d_tmp (4N doubles) and d_out[0..7].
+int fields_and_reduce(lbm_ctx *c)
+{
+    int rc = ensure_tmp(c, (size_t)c->N * 4 * sizeof(double));
+    if (rc) return rc;
+    int nparts = 0;
+    rc = run_pass(c, P_FIELDS_REDUCE, c->d_tmp, nullptr, nullptr, nullptr, &nparts);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->d_partials, nparts, c->d_out);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+}  // namespace lbm_host
+
+using namespace lbm_host;
+
+extern "C" {
+
+int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (nx < 5 || ny < 5 || (long long)nx * ny > (1LL << 30)) return LBM_EINVAL;
+    if (storage < LBM_F64 || storage > LBM_BF16) return LBM_EINVAL;
+    if (flags & ~127u) return LBM_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LBM_EDEVICE;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    c->nx = nx;
+    c->ny = ny;
+    c->storage = storage;
+    c->flags = flags;
+    c->N = (long long)nx * ny;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    const size_t bytes = (size_t)c->N * 18 * elem_size(storage);
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return LBM_EDEVICE;
+    }
+    c->stream = c->own_stream;
+    bool ok = hipMalloc(&c->buf[0], bytes) == hipSuccess && hipMalloc(&c->buf[1], bytes) == hipSuccess &&
+              hipMalloc(&c->d_solid, (size_t)c->N) == hipSuccess && hipMalloc(&c->d_out, 16 * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        lbm_destroy(c);
+        return LBM_ENOMEM;
+    }
+    c->solid.assign((size_t)c->N, 0);
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->buf[0]) (void)hipFree(c->buf[0]);
+    if (c->buf[1]) (void)hipFree(c->buf[1]);
+    if (c->d_solid) (void)hipFree(c->d_solid);
+    if (c->d_tmp) (void)hipFree(c->d_tmp);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_out) (void)hipFree(c->d_out);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int lbm_set_stream(lbm_ctx *c, void *hip_stream)
+{
+    if (!c) return LBM_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
+    return LBM_OK;
+}
+
+int lbm_set_geometry(lbm_ctx *c, const uint8_t *solid)
+{
+    if (!c || !solid) return LBM_EINVAL;
+    long long nf = 0;
+    for (long long i = 0; i < c->N; ++i) {
+        c->solid[(size_t)i] = solid[i] ? 1 : 0;
+        nf += solid[i] ? 0 : 1;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_solid, c->solid.data(), (size_t)c->N, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->n_fluid = nf;
+    c->have_geom = true;
+    c->have_fields = false;
+    return LBM_OK;
+}
+
+int lbm_set_params(lbm_ctx *c, double G_c, double G_ads, double tau)
+{
+    if (!c) return LBM_EINVAL;
+    if (!(tau > 0.5) || !std::isfinite(tau)) return set_err(c, LBM_EINVAL, "tau must be > 0.5");
+    if (!std::isfinite(G_c) || !std::isfinite(G_ads)) return set_err(c, LBM_EINVAL, "non-finite parameter");
+    const double Gw2 = G_c, Gw1 = G_c + 2.0 * G_ads;
+    if (!(c->flags & LBM_SCHEME_ORIGINAL) && !(Gw2 != 0.0 && Gw1 / Gw2 > 0.0))
+        return set_err(c, LBM_EINVAL, "lambda = 1 + 2 G_ads / G_c must be > 0");
+    int rc = check_adhesion(c, Gw1, Gw2, 0.8);
+    if (rc) return rc;
+    c->Gc = G_c;
+    c->Gw1 = Gw1;
+    c->Gw2 = Gw2;
+    c->delta = 0.8;
+    c->tau = tau;
+    c->have_params = true;
+    return LBM_OK;
+}
+
+int lbm_set_adhesion(lbm_ctx *c, double G_w1, double G_w2, double delta)
+{
+    if (!c) return LBM_EINVAL;
+    if (!c->have_params) return set_err(c, LBM_ESTATE, "set_params first");
+    int rc = check_adhesion(c, G_w1, G_w2, delta);
+    if (rc) return rc;
+    c->Gw1 = G_w1;
+    c->Gw2 = G_w2;
+    c->delta = delta;
+    return LBM_OK;
+}
+
+int lbm_set_body_accel(lbm_ctx *c, double g1x, double g1y, double g2x, double g2y)
+{
+    if (!c) return LBM_EINVAL;
+    if (!std::isfinite(g1x) || !std::isfinite(g1y) || !std::isfinite(g2x) || !std::isfinite(g2y))
+        return set_err(c, LBM_EINVAL, "non-finite acceleration");
+    c->acc[0][0] = g1x;
+    c->acc[0][1] = g1y;
+    c->acc[1][0] = g2x;
+    c->acc[1][1] = g2y;
+    return LBM_OK;
+}
+
+int lbm_init_fields(lbm_ctx *c, const double *rho1, const double *rho2)
+{
+    if (!c || !rho1 || !rho2) return LBM_EINVAL;
+    if (!c->have_geom) return set_err(c, LBM_ESTATE, "set_geometry first");
+    double s[2] = {0, 0};
+    for (long long i = 0; i < c->N; ++i) {
+        if (c->solid[(size_t)i]) continue;
+        if (!std::isfinite(rho1[i]) || !std::isfinite(rho2[i])) return set_err(c, LBM_EINVAL, "non-finite density");
+        s[0] += rho1[i];
+        s[1] += rho2[i];
+    }
+    c->rho0[0] = c->n_fluid ? s[0] / (double)c->n_fluid : 0.0;
+    c->rho0[1] = c->n_fluid ? s[1] / (double)c->n_fluid : 0.0;
+    int rc = ensure_tmp(c, (size_t)c->N * 2 * sizeof(double));
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->d_tmp, rho1, (size_t)c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_tmp + c->N, rho2, (size_t)c->N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const size_t bytes = (size_t)c->N * 18 * elem_size(c->storage);
+    HIPCHK(c, hipMemsetAsync(c->buf[0], 0xff, bytes, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->buf[1], 0xff, bytes, c->stream));
+    c->cur = 0;
+    rc = inverse_stream(c, nullptr, c->d_tmp);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_fields = true;
+    c->t = 0;
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx *c, const double *f)
+{
+    if (!c || !f) return LBM_EINVAL;
+    if (!c->have_geom) return set_err(c, LBM_ESTATE, "set_geometry first");
+    double s[2] = {0, 0};
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 9; ++i)
+            for (long long z = 0; z < c->N; ++z) {
+                if (c->solid[(size_t)z]) continue;
+                const double v = f[(size_t)(k * 9 + i) * c->N + z];
+                if (!std::isfinite(v)) return set_err(c, LBM_EINVAL, "non-finite population");
+                s[k] += v;
+            }
+    c->rho0[0] = c->n_fluid ? s[0] / (double)c->n_fluid : 0.0;
+    c->rho0[1] = c->n_fluid ? s[1] / (double)c->n_fluid : 0.0;
+    int rc = ensure_tmp(c, (size_t)c->N * 18 * sizeof(double));
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->d_tmp, f, (size_t)c->N * 18 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    const size_t bytes = (size_t)c->N * 18 * elem_size(c->storage);
+    HIPCHK(c, hipMemsetAsync(c->buf[0], 0xff, bytes, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->buf[1], 0xff, bytes, c->stream));
+    c->cur = 0;
+    rc = inverse_stream(c, c->d_tmp, nullptr);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_fields = true;
+    c->t = 0;
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx *c, double *f)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!f) return set_err(c, LBM_EINVAL, "null output");
+    rc = ensure_tmp(c, (size_t)c->N * 18 * sizeof(double));
+    if (rc) return rc;
+    rc = pull_populations(c, c->d_tmp);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(f, c->d_tmp, (size_t)c->N * 18 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_get_populations_window(lbm_ctx *c, int x0, int y0, int w, int h, double *f)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!f || w < 1 || h < 1) return set_err(c, LBM_EINVAL, "bad window");
+    const bool px = c->flags & LBM_PERIODIC_X, py = c->flags & LBM_PERIODIC_Y;
+    if ((!px && (x0 < 0 || (long long)x0 + w > c->nx)) || (!py && (y0 < 0 || (long long)y0 + h > c->ny)) ||
+        (long long)w * h > c->N * 4)
+        return set_err(c, LBM_EINVAL, "window leaves the domain");
+    const size_t bytes = (size_t)w * h * 18 * sizeof(double);
+    rc = ensure_tmp(c, bytes);
+    if (rc) return rc;
+    rc = pull_window(c, x0, y0, w, h, c->d_tmp);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(f, c->d_tmp, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int n)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
+    for (int s = 0; s < n; ++s) {
+        rc = run_pass(c, P_STEP, nullptr, nullptr, nullptr, nullptr, nullptr);
+        if (rc) return rc;
+        c->cur ^= 1;
+        c->t += 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_synchronize(lbm_ctx *c)
+{
+    if (!c) return LBM_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+long lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+int lbm_get_fields(lbm_ctx *c, double *rho1, double *rho2, double *ux, double *uy)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    rc = fields_and_reduce(c);
+    if (rc) return rc;
+    double *outs[4] = {rho1, rho2, ux, uy};
+    for (int q = 0; q < 4; ++q)
+        if (outs[q])
+            HIPCHK(c, hipMemcpyAsync(outs[q], c->d_tmp + (size_t)q * c->N, (size_t)c->N * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_reduce(lbm_ctx *c, double out[8])
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!out) return set_err(c, LBM_EINVAL, "null output");
+    rc = fields_and_reduce(c);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(out, c->d_out, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->n_fluid == 0) {
+        out[5] = 0.0;
+        out[6] = 0.0;
+    }
+    return LBM_OK;
+}
+
+int lbm_contact_angle(lbm_ctx *c, int wall_kind, const double wall[3], double *theta_deg)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!wall || !theta_deg || (wall_kind != LBM_WALL_FLAT && wall_kind != LBM_WALL_CYLINDER))
+        return set_err(c, LBM_EINVAL, "bad wall description");
+    rc = fields_and_reduce(c);
+    if (rc) return rc;
+    int dims_h[2] = {c->nx, c->ny};
+    long long off_h = 0;
+    WallDesc wd = {wall_kind, wall[0], wall[1], wall[2]};
+    // small argument block placed after the 4 field arrays would need more
+    // staging; use a dedicated tiny allocation instead
+    struct Args {
+        int dims[2];
+        long long off;
+        WallDesc wd;
+    } args_h = {{dims_h[0], dims_h[1]}, off_h, wd};
+    Args *d_args = nullptr;
+    HIPCHK(c, hipMalloc(&d_args, sizeof(Args)));
+    hipError_t e = hipMemcpyAsync(d_args, &args_h, sizeof(Args), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_contact_angle, dim3(1), dim3(256), 0, c->stream, (const int *)d_args->dims,
+                           (const long long *)&d_args->off, c->d_tmp, c->d_tmp + c->N, c->d_solid,
+                           (const WallDesc *)&d_args->wd, c->d_out + 8);
+        e = hipGetLastError();
+    }
+    double res[6] = {0, 0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(res, c->d_out + 8, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d_args);
+    if (e != hipSuccess) return set_err(c, LBM_EDEVICE, "contact angle failed: %s", hipGetErrorString(e));
+    if (res[5] == 1.0) return set_err(c, LBM_EUNSTABLE, "fewer than 3 interface points");
+    if (res[5] != 0.0) return set_err(c, LBM_EUNSTABLE, "circle fit failed");
+    *theta_deg = res[0];
+    return LBM_OK;
+}
+
+int lbm_get_tables(lbm_ctx *c, uint8_t *link, int32_t *nw_list, int32_t *nw_src, int *n_nw)
+{
+    if (!c) return LBM_EINVAL;
+    if (!c->have_geom || !c->have_fields)
+        return set_err(c, LBM_ESTATE, "tables are derived from an initialised lattice");
+    const size_t N = (size_t)c->N;
+    int rc = ensure_tmp(c, N * (2 + 24 * sizeof(int32_t)) + 64);
+    if (rc) return rc;
+    uint8_t *d_link = (uint8_t *)c->d_tmp;
+    uint8_t *d_nw = d_link + N;
+    int32_t *d_src = (int32_t *)(((uintptr_t)(d_nw + N) + 63) & ~(uintptr_t)63);
+    HIPCHK(c, hipMemsetAsync(d_link, 0, 2 * N, c->stream));
+    rc = run_pass(c, P_TABLES, nullptr, d_link, d_nw, d_src, nullptr);
+    if (rc) return rc;
+    std::vector<uint8_t> h_link(N), h_nw(N);
+    std::vector<int32_t> h_src;
+    HIPCHK(c, hipMemcpyAsync(h_link.data(), d_link, N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h_nw.data(), d_nw, N, hipMemcpyDeviceToHost, c->stream));
+    if (nw_list && nw_src) {
+        h_src.resize(N * 24);
+        HIPCHK(c, hipMemcpyAsync(h_src.data(), d_src, N * 24 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (link) std::memcpy(link, h_link.data(), N);
+    int count = 0;
+    for (size_t z = 0; z < N; ++z) {
+        if (!h_nw[z]) continue;
+        if (nw_list) {
+            nw_list[count] = (int32_t)z;
+            if (nw_src) std::memcpy(nw_src + (size_t)count * 24, h_src.data() + z * 24, 24 * sizeof(int32_t));
+        }
+        ++count;
+    }
+    if (n_nw) *n_nw = count;
+    return LBM_OK;
+}
+
+int lbm_set_tile(lbm_ctx *c, int block, int seg_rows)
+{
+    if (!c) return LBM_EINVAL;
+    if (!valid_block(block) || seg_rows < 1) return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 1");
+    c->block = block;
+    c->seg_rows = seg_rows;
+    return LBM_OK;
+}
+
+int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows)
+{
+    if (!c) return LBM_EINVAL;
+    if (block) *block = c->block;
+    if (seg_rows) *seg_rows = c->seg_rows;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx *c, int steps)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (steps < 1) return set_err(c, LBM_EINVAL, "steps must be >= 1");
+    const size_t bytes = (size_t)c->N * 18 * elem_size(c->storage);
+    void *backup = nullptr;
+    if (hipMalloc(&backup, bytes) != hipSuccess) return set_err(c, LBM_ENOMEM, "autotune backup allocation failed");
+    const int cur0 = c->cur;
+    const long t0 = c->t;
+    hipError_t e = hipMemcpyAsync(backup, c->buf[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    const int blocks[3] = {64, 128, 256};
+    const int rows[7] = {8, 16, 32, 64, 128, 256, 512};
+    int best_b = c->block, best_r = c->seg_rows;
+    float best_ms = 1e30f;
+    for (int bi = 0; bi < 3 && e == hipSuccess && rc == LBM_OK; ++bi)
+        for (int ri = 0; ri < 7 && e == hipSuccess && rc == LBM_OK; ++ri) {
+            if (rows[ri] > c->ny && ri > 0) continue;
+            c->block = blocks[bi];
+            c->seg_rows = rows[ri];
+            rc = lbm_step(c, 1);  // warm-up
+            if (rc) break;
+            e = hipEventRecord(ev0, c->stream);
+            if (e != hipSuccess) break;
+            rc = lbm_step(c, steps);
+            if (rc) break;
+            e = hipEventRecord(ev1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best_b = blocks[bi];
+                best_r = rows[ri];
+            }
+        }
+    if (e == hipSuccess) e = hipMemcpyAsync(c->buf[cur0], backup, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFree(backup);
+    c->cur = cur0;
+    c->t = t0;
+    c->block = best_b;
+    c->seg_rows = best_r;
+    if (rc) return rc;
+    if (e != hipSuccess) return set_err(c, LBM_EDEVICE, "autotune failed: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// Checkpoint file: header, then the raw post-collision buffer.
+struct CkptHeader {
+    char magic[8];
+    int version, nx, ny, storage;
+    unsigned flags;
+    long long t;
+    double Gc, Gw1, Gw2, delta, tau, acc[4], rho0[2];
+};
+
+int lbm_save(lbm_ctx *c, const char *path)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!path) return set_err(c, LBM_EINVAL, "null path");
+    const size_t bytes = (size_t)c->N * 18 * elem_size(c->storage);
+    std::vector<char> host(bytes);
+    HIPCHK(c, hipMemcpyAsync(host.data(), c->buf[c->cur], bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    CkptHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "LBM2CPK", 8);
+    h.version = 1;
+    h.nx = c->nx;
+    h.ny = c->ny;
+    h.storage = c->storage;
+    h.flags = c->flags;
+    h.t = c->t;
+    h.Gc = c->Gc;
+    h.Gw1 = c->Gw1;
+    h.Gw2 = c->Gw2;
+    h.delta = c->delta;
+    h.tau = c->tau;
+    h.acc[0] = c->acc[0][0];
+    h.acc[1] = c->acc[0][1];
+    h.acc[2] = c->acc[1][0];
+    h.acc[3] = c->acc[1][1];
+    h.rho0[0] = c->rho0[0];
+    h.rho0[1] = c->rho0[1];
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp) return set_err(c, LBM_EIO, "cannot open %s", path);
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(c->solid.data(), 1, (size_t)c->N, fp) == (size_t)c->N &&
+              std::fwrite(host.data(), 1, bytes, fp) == bytes;
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return set_err(c, LBM_EIO, "write to %s failed", path);
+    return LBM_OK;
+}
+
+int lbm_load(lbm_ctx *c, const char *path)
+{
+    if (!c || !path) return LBM_EINVAL;
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return set_err(c, LBM_EIO, "cannot open %s", path);
+    CkptHeader h;
+    const size_t bytes = (size_t)c->N * 18 * elem_size(c->storage);
+    std::vector<uint8_t> sol((size_t)c->N);
+    std::vector<char> host(bytes);
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1;
+    if (ok && (std::memcmp(h.magic, "LBM2CPK", 8) != 0 || h.version != 1 || h.nx != c->nx || h.ny != c->ny ||
+               h.storage != c->storage || h.flags != c->flags)) {
+        std::fclose(fp);
+        return set_err(c, LBM_EINVAL, "checkpoint does not match this context");
+    }
+    ok = ok && std::fread(sol.data(), 1, (size_t)c->N, fp) == (size_t)c->N && std::fread(host.data(), 1, bytes, fp) == bytes;
+    std::fclose(fp);
+    if (!ok) return set_err(c, LBM_EIO, "short read from %s", path);
+    int rc = lbm_set_geometry(c, sol.data());
+    if (rc) return rc;
+    c->Gc = h.Gc;
+    c->Gw1 = h.Gw1;
+    c->Gw2 = h.Gw2;
+    c->delta = h.delta;
+    c->tau = h.tau;
+    c->acc[0][0] = h.acc[0];
+    c->acc[0][1] = h.acc[1];
+    c->acc[1][0] = h.acc[2];
+    c->acc[1][1] = h.acc[3];
+    c->rho0[0] = h.rho0[0];
+    c->rho0[1] = h.rho0[1];
+    c->have_params = true;
+    HIPCHK(c, hipMemcpyAsync(c->buf[0], host.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->buf[1], 0xff, bytes, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cur = 0;
+    c->t = (long)h.t;
+    c->have_fields = true;
+    return LBM_OK;
+}
+
+long lbm_fluid_nodes(const lbm_ctx *c) { return c ? (long)c->n_fluid : -1; }
+
+int lbm_bytes_per_update(const lbm_ctx *c)
+{
+    if (!c) return LBM_EINVAL;
+    return (int)(2 * 9 * 2 * elem_size(c->storage) + 1);
+}
+
+}  // extern "C"

@@ -1,0 +1,485 @@
+// Batched runs (include/lbm.h, lbm_batch_*): many independent lattices of
+// uneven sizes and parameters advanced by one kernel launch per time step.
+// The work list concatenates every run's (strip, segment) items; the batched
+// kernel finds the owning run by binary search over item offsets and then
+// executes exactly the per-item code of the single-run kernel, so a run's
+// result is bitwise that of a single context.  Optionally a HIP graph of
+// several steps is captured once and replayed.
+#include "lbm.h"
+#include "lbm_kernels.hpp"
+#include "lbm_params.hpp"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbm;
+using namespace lbm_host;
+
+struct BatchRun {
+    int nx, ny;
+    unsigned flags;
+    double Gc, Gw1, Gw2, tau;
+    double acc[2][2];
+    double rho0[2];
+    int wall_kind;
+    double wall[3];
+    long long off;       // node offset into the concatenated arrays
+    long long n_fluid;
+    int item0, strips, segs;
+};
+
+struct lbm_batch {
+    int nruns = 0, storage = 0;
+    int block = 256, seg_rows = 64;
+    std::vector<BatchRun> runs;
+    long long total_nodes = 0, total_fluid = 0;
+    int n_items = 0;
+    void *buf[2] = {nullptr, nullptr};
+    int flip = 0;  // 0: runs read buf[0]
+    void *d_params = nullptr;
+    uint8_t *d_solid = nullptr;
+    double *d_fields = nullptr;  // 4 * total_nodes
+    double *d_partials = nullptr;
+    size_t partials_cap = 0;
+    int *d_dims = nullptr;
+    long long *d_offs = nullptr;
+    WallDesc *d_walls = nullptr;
+    double *d_out = nullptr;
+    hipStream_t stream = nullptr, own_stream = nullptr;
+    bool use_graph = false;
+    int graph_steps = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+namespace {
+
+int berr(lbm_batch *b, int code, const char *fmt, ...)
+{
+    if (b) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        b->err = buf;
+    }
+    return code;
+}
+
+#define BCHK(b, call)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return berr((b), LBM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t esize(int storage) { return storage == LBM_F64 ? 8 : storage == LBM_F32 ? 4 : 2; }
+
+void drop_graphs(lbm_batch *b)
+{
+    for (int q = 0; q < 2; ++q) {
+        if (b->gexec[q]) (void)hipGraphExecDestroy(b->gexec[q]);
+        if (b->graph[q]) (void)hipGraphDestroy(b->graph[q]);
+        b->gexec[q] = nullptr;
+        b->graph[q] = nullptr;
+    }
+}
+
+template <class C>
+KParams<C> run_params(const lbm_batch *b, const BatchRun &r, int storage, int block, int seg_rows, int flip)
+{
+    KParams<C> p;
+    std::memset(&p, 0, sizeof p);
+    const size_t es = esize(storage);
+    char *b0 = (char *)b->buf[flip], *b1 = (char *)b->buf[flip ^ 1];
+    p.A = b0 + (size_t)r.off * 18 * es;
+    p.B = b1 + (size_t)r.off * 18 * es;
+    p.nx = r.nx;
+    p.ny = r.ny;
+    p.flags = r.flags;
+    tile_counts(block, seg_rows, r.nx, r.ny, &p.n_strips, &p.n_segs);
+    p.item0 = r.item0;
+    p.N = (long long)r.nx * r.ny;
+    fill_physics<C>(p, r.flags, r.Gc, r.Gw1, r.Gw2, 0.8, r.tau, r.acc, r.rho0, storage != LBM_F64);
+    return p;
+}
+
+// Recompute the work list and upload the per-run parameter records (with
+// A = buf[0] side; the kernel swaps A/B when flip is set).
+template <int S>
+int upload_params_t(lbm_batch *b)
+{
+    using C = typename Traits<S>::C;
+    std::vector<KParams<C>> h((size_t)b->nruns);
+    int item = 0;
+    for (int r = 0; r < b->nruns; ++r) {
+        BatchRun &br = b->runs[(size_t)r];
+        br.item0 = item;
+        tile_counts(b->block, b->seg_rows, br.nx, br.ny, &br.strips, &br.segs);
+        item += br.strips * br.segs;
+        h[(size_t)r] = run_params<C>(b, br, b->storage, b->block, b->seg_rows, 0);
+    }
+    b->n_items = item;
+    if (b->d_params) (void)hipFree(b->d_params);
+    b->d_params = nullptr;
+    BCHK(b, hipMalloc(&b->d_params, h.size() * sizeof(KParams<C>)));
+    BCHK(b, hipMemcpy(b->d_params, h.data(), h.size() * sizeof(KParams<C>), hipMemcpyHostToDevice));
+    drop_graphs(b);
+    return LBM_OK;
+}
+
+int upload_params(lbm_batch *b)
+{
+    switch (b->storage) {
+    case LBM_F64: return upload_params_t<ST_F64>(b);
+    case LBM_F32: return upload_params_t<ST_F32>(b);
+    case LBM_F16: return upload_params_t<ST_F16>(b);
+    default: return upload_params_t<ST_BF16>(b);
+    }
+}
+
+template <int S, int BLOCK>
+hipError_t launch_batch_t(lbm_batch *b, int flip)
+{
+    using C = typename Traits<S>::C;
+    const int per_xcd = (b->n_items + 7) / 8;
+    hipLaunchKernelGGL((k_step_batch<S, BLOCK, M_STORE>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream,
+                       (const KParams<C> *)b->d_params, b->nruns, b->n_items, per_xcd, flip);
+    return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_batch_s(lbm_batch *b, int flip)
+{
+    switch (b->block) {
+    case 64: return launch_batch_t<S, 64>(b, flip);
+    case 128: return launch_batch_t<S, 128>(b, flip);
+    default: return launch_batch_t<S, 256>(b, flip);
+    }
+}
+
+hipError_t launch_batch(lbm_batch *b, int flip)
+{
+    switch (b->storage) {
+    case LBM_F64: return launch_batch_s<ST_F64>(b, flip);
+    case LBM_F32: return launch_batch_s<ST_F32>(b, flip);
+    case LBM_F16: return launch_batch_s<ST_F16>(b, flip);
+    default: return launch_batch_s<ST_BF16>(b, flip);
+    }
+}
+
+template <int S>
+int init_run_t(lbm_batch *b, int r, const double *d_rho)
+{
+    using C = typename Traits<S>::C;
+    const BatchRun &br = b->runs[(size_t)r];
+    KParams<C> p = run_params<C>(b, br, b->storage, 256, 64, 1);  // B = buf[0] side
+    const long long N = (long long)br.nx * br.ny;
+    hipLaunchKernelGGL((k_inverse_stream<S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, b->stream, p,
+                       b->d_solid + br.off, (const double *)nullptr, d_rho);
+    BCHK(b, hipGetLastError());
+    return LBM_OK;
+}
+
+int init_run(lbm_batch *b, int r, const double *d_rho)
+{
+    switch (b->storage) {
+    case LBM_F64: return init_run_t<ST_F64>(b, r, d_rho);
+    case LBM_F32: return init_run_t<ST_F32>(b, r, d_rho);
+    case LBM_F16: return init_run_t<ST_F16>(b, r, d_rho);
+    default: return init_run_t<ST_BF16>(b, r, d_rho);
+    }
+}
+
+// Fields of run r (at the batch's current time) into d_fields at its offset.
+template <int S>
+int fields_run_t(lbm_batch *b, int r)
+{
+    using C = typename Traits<S>::C;
+    const BatchRun &br = b->runs[(size_t)r];
+    KParams<C> p = run_params<C>(b, br, b->storage, 256, 64, b->flip);
+    const long long T = b->total_nodes;
+    p.out_rho1 = b->d_fields + br.off;
+    p.out_rho2 = b->d_fields + T + br.off;
+    p.out_ux = b->d_fields + 2 * T + br.off;
+    p.out_uy = b->d_fields + 3 * T + br.off;
+    const int grid = ((p.n_strips * p.n_segs + 7) / 8) * 8;
+    if (b->partials_cap < (size_t)grid) {
+        if (b->d_partials) (void)hipFree(b->d_partials);
+        b->d_partials = nullptr;
+        b->partials_cap = 0;
+        BCHK(b, hipMalloc(&b->d_partials, (size_t)grid * 8 * sizeof(double)));
+        b->partials_cap = (size_t)grid;
+    }
+    p.partials = b->d_partials;
+    hipLaunchKernelGGL((k_step<S, 256, M_FIELDS | M_REDUCE>), dim3(grid), dim3(256), 0, b->stream, p, grid / 8);
+    BCHK(b, hipGetLastError());
+    return LBM_OK;
+}
+
+int fields_run(lbm_batch *b, int r)
+{
+    switch (b->storage) {
+    case LBM_F64: return fields_run_t<ST_F64>(b, r);
+    case LBM_F32: return fields_run_t<ST_F32>(b, r);
+    case LBM_F16: return fields_run_t<ST_F16>(b, r);
+    default: return fields_run_t<ST_BF16>(b, r);
+    }
+}
+
+int capture_graph(lbm_batch *b, int parity)
+{
+    BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < b->graph_steps && e == hipSuccess; ++s) e = launch_batch(b, (parity + s) & 1);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return berr(b, LBM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph[parity] = g;
+    BCHK(b, hipGraphInstantiate(&b->gexec[parity], g, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int storage)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    if (nruns < 1 || !runs || storage < LBM_F64 || storage > LBM_BF16) return LBM_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LBM_EDEVICE;
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_ENOMEM;
+    b->nruns = nruns;
+    b->storage = storage;
+    b->runs.resize((size_t)nruns);
+    long long off = 0;
+    for (int r = 0; r < nruns; ++r) {
+        const lbm_run_desc &d = runs[r];
+        BatchRun &br = b->runs[(size_t)r];
+        if (d.nx < 5 || d.ny < 5 || !d.solid || !d.rho1 || !d.rho2 || (d.flags & ~127u) || !(d.tau > 0.5) ||
+            !std::isfinite(d.tau) || !std::isfinite(d.G_c) || !std::isfinite(d.G_ads) ||
+            (d.wall_kind != LBM_WALL_FLAT && d.wall_kind != LBM_WALL_CYLINDER)) {
+            delete b;
+            return LBM_EINVAL;
+        }
+        br.nx = d.nx;
+        br.ny = d.ny;
+        br.flags = d.flags;
+        br.Gc = d.G_c;
+        br.Gw2 = d.G_c;
+        br.Gw1 = d.G_c + 2.0 * d.G_ads;
+        if (!(d.flags & LBM_SCHEME_ORIGINAL) && !(br.Gw2 != 0.0 && br.Gw1 / br.Gw2 > 0.0 && br.Gw1 + br.Gw2 != 0.0)) {
+            delete b;
+            return LBM_EINVAL;
+        }
+        br.tau = d.tau;
+        for (int q = 0; q < 4; ++q) br.acc[q / 2][q % 2] = d.accel ? d.accel[q] : 0.0;
+        br.wall_kind = d.wall_kind;
+        for (int q = 0; q < 3; ++q) br.wall[q] = d.wall[q];
+        br.off = off;
+        const long long N = (long long)d.nx * d.ny;
+        off += N;
+        double s[2] = {0, 0};
+        long long nf = 0;
+        for (long long z = 0; z < N; ++z) {
+            if (d.solid[z]) continue;
+            if (!std::isfinite(d.rho1[z]) || !std::isfinite(d.rho2[z])) {
+                delete b;
+                return LBM_EINVAL;
+            }
+            s[0] += d.rho1[z];
+            s[1] += d.rho2[z];
+            ++nf;
+        }
+        br.n_fluid = nf;
+        br.rho0[0] = nf ? s[0] / (double)nf : 0.0;
+        br.rho0[1] = nf ? s[1] / (double)nf : 0.0;
+        b->total_fluid += nf;
+    }
+    b->total_nodes = off;
+    const size_t bytes = (size_t)off * 18 * esize(storage);
+    bool ok = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking) == hipSuccess;
+    b->stream = b->own_stream;
+    ok = ok && hipMalloc(&b->buf[0], bytes) == hipSuccess && hipMalloc(&b->buf[1], bytes) == hipSuccess &&
+         hipMalloc(&b->d_solid, (size_t)off) == hipSuccess &&
+         hipMalloc(&b->d_fields, (size_t)off * 4 * sizeof(double)) == hipSuccess &&
+         hipMalloc(&b->d_dims, (size_t)nruns * 2 * sizeof(int)) == hipSuccess &&
+         hipMalloc(&b->d_offs, (size_t)nruns * sizeof(long long)) == hipSuccess &&
+         hipMalloc(&b->d_walls, (size_t)nruns * sizeof(WallDesc)) == hipSuccess &&
+         hipMalloc(&b->d_out, (size_t)nruns * 6 * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        lbm_batch_destroy(b);
+        return LBM_ENOMEM;
+    }
+    std::vector<uint8_t> hsolid((size_t)off);
+    std::vector<double> hrho;
+    std::vector<int> dims((size_t)nruns * 2);
+    std::vector<long long> offs((size_t)nruns);
+    std::vector<WallDesc> walls((size_t)nruns);
+    for (int r = 0; r < nruns; ++r) {
+        const BatchRun &br = b->runs[(size_t)r];
+        const long long N = (long long)br.nx * br.ny;
+        for (long long z = 0; z < N; ++z) hsolid[(size_t)(br.off + z)] = runs[r].solid[z] ? 1 : 0;
+        dims[(size_t)2 * r] = br.nx;
+        dims[(size_t)2 * r + 1] = br.ny;
+        offs[(size_t)r] = br.off;
+        walls[(size_t)r] = WallDesc{br.wall_kind, br.wall[0], br.wall[1], br.wall[2]};
+    }
+    hipError_t e = hipMemcpy(b->d_solid, hsolid.data(), (size_t)off, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_dims, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_offs, offs.data(), offs.size() * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_walls, walls.data(), walls.size() * sizeof(WallDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->buf[0], 0xff, bytes);
+    if (e == hipSuccess) e = hipMemset(b->buf[1], 0xff, bytes);
+    if (e != hipSuccess) {
+        lbm_batch_destroy(b);
+        return LBM_EDEVICE;
+    }
+    int rc = upload_params(b);
+    // initial populations, run by run (densities staged in d_fields)
+    for (int r = 0; r < nruns && rc == LBM_OK; ++r) {
+        const BatchRun &br = b->runs[(size_t)r];
+        const long long N = (long long)br.nx * br.ny;
+        if (hipMemcpy(b->d_fields, runs[r].rho1, (size_t)N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b->d_fields + N, runs[r].rho2, (size_t)N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = LBM_EDEVICE;
+            break;
+        }
+        rc = init_run(b, r, b->d_fields);
+        if (rc == LBM_OK && hipStreamSynchronize(b->stream) != hipSuccess) rc = LBM_EDEVICE;
+    }
+    if (rc) {
+        lbm_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    void *ptrs[] = {b->buf[0], b->buf[1], b->d_params, b->d_solid, b->d_fields, b->d_partials,
+                    b->d_dims, b->d_offs, b->d_walls, b->d_out};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+    delete b;
+}
+
+const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+long lbm_batch_fluid_nodes(const lbm_batch *b) { return b ? (long)b->total_fluid : -1; }
+
+int lbm_batch_set_stream(lbm_batch *b, void *hip_stream)
+{
+    if (!b) return LBM_EINVAL;
+    BCHK(b, hipStreamSynchronize(b->stream));
+    b->stream = hip_stream ? (hipStream_t)hip_stream : b->own_stream;
+    drop_graphs(b);
+    return LBM_OK;
+}
+
+int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows)
+{
+    if (!b) return LBM_EINVAL;
+    if (!(block == 64 || block == 128 || block == 256) || seg_rows < 1)
+        return berr(b, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 1");
+    b->block = block;
+    b->seg_rows = seg_rows;
+    return upload_params(b);
+}
+
+int lbm_batch_use_graph(lbm_batch *b, int use_graph, int steps_per_graph)
+{
+    if (!b) return LBM_EINVAL;
+    if (use_graph && steps_per_graph < 1) return berr(b, LBM_EINVAL, "steps_per_graph must be >= 1");
+    drop_graphs(b);
+    b->use_graph = use_graph != 0;
+    b->graph_steps = use_graph ? steps_per_graph : 0;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int n)
+{
+    if (!b) return LBM_EINVAL;
+    if (n < 0) return berr(b, LBM_EINVAL, "negative step count");
+    int s = 0;
+    if (b->use_graph) {
+        while (n - s >= b->graph_steps) {
+            const int parity = b->flip;
+            if (!b->gexec[parity]) {
+                int rc = capture_graph(b, parity);
+                if (rc) return rc;
+            }
+            BCHK(b, hipGraphLaunch(b->gexec[parity], b->stream));
+            s += b->graph_steps;
+            b->flip = (b->flip + b->graph_steps) & 1;
+        }
+    }
+    for (; s < n; ++s) {
+        BCHK(b, launch_batch(b, b->flip));
+        b->flip ^= 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_get_fields(lbm_batch *b, int run, double *rho1, double *rho2, double *ux, double *uy)
+{
+    if (!b) return LBM_EINVAL;
+    if (run < 0 || run >= b->nruns) return berr(b, LBM_EINVAL, "run index out of range");
+    int rc = fields_run(b, run);
+    if (rc) return rc;
+    const BatchRun &br = b->runs[(size_t)run];
+    const long long N = (long long)br.nx * br.ny, T = b->total_nodes;
+    double *outs[4] = {rho1, rho2, ux, uy};
+    for (int q = 0; q < 4; ++q)
+        if (outs[q])
+            BCHK(b, hipMemcpyAsync(outs[q], b->d_fields + q * T + br.off, (size_t)N * sizeof(double),
+                                   hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+int lbm_batch_contact_angles(lbm_batch *b, double *theta_deg)
+{
+    if (!b || !theta_deg) return LBM_EINVAL;
+    for (int r = 0; r < b->nruns; ++r) {
+        int rc = fields_run(b, r);
+        if (rc) return rc;
+    }
+    const long long T = b->total_nodes;
+    hipLaunchKernelGGL(k_contact_angle, dim3(b->nruns), dim3(256), 0, b->stream, b->d_dims, b->d_offs, b->d_fields,
+                       b->d_fields + T, b->d_solid, b->d_walls, b->d_out);
+    BCHK(b, hipGetLastError());
+    std::vector<double> res((size_t)b->nruns * 6);
+    BCHK(b, hipMemcpyAsync(res.data(), b->d_out, res.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    int rc = LBM_OK;
+    for (int r = 0; r < b->nruns; ++r) {
+        if (res[(size_t)r * 6 + 5] != 0.0) {
+            theta_deg[r] = NAN;
+            rc = LBM_EUNSTABLE;
+        } else {
+            theta_deg[r] = res[(size_t)r * 6];
+        }
+    }
+    if (rc) berr(b, rc, "contact angle failed for at least one run (NaN entries)");
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,324 @@
+// Device building blocks of the fused two-component pseudopotential LBM
+// step for gfx950 (arXiv 2505.22256, Sec. 2.1-2.4, Eq. 1-12, Table 1).
+//
+// Data layout in HBM: one population set per buffer, structure of arrays
+// [component k][direction i][node], node = y*nx + x.  Solid nodes carry an
+// all-ones bit pattern (a NaN that arithmetic never produces) in every
+// population slot, so the step kernel reads no geometry array: a pulled
+// sentinel marks a solid source (bounce-back), a sentinel at the node's own
+// rest slot marks a solid node, and a sentinel psi in the LDS tile marks an
+// unavailable stencil position.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Storage : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+enum : unsigned {
+    FL_PERIODIC_X = 1u,
+    FL_PERIODIC_Y = 2u,
+    FL_ORIGINAL = 4u,
+    FL_COPY_OFF = 8u,
+    FL_WALLPSI_SELF = 16u,
+    FL_VEL_LITERAL = 32u,
+    FL_FORCE_DENSITY = 64u
+};
+
+// Kernel modes (bit set).
+enum : int {
+    M_STORE = 1,   // collide and write the post-collision set
+    M_REDUCE = 2,  // per-workgroup diagnostic partial sums
+    M_FIELDS = 4,  // write rho_1, rho_2, u (FP64)
+    M_TABLES = 8   // write link bits and resolved stencil sources
+};
+
+// ---------------------------------------------------------------------------
+// D2Q9 and E8 constants
+// ---------------------------------------------------------------------------
+// D2Q9: e_0 = 0, e_1..4 axis links, e_5..8 diagonals.
+__host__ __device__ constexpr int qx(int i) { return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0); }
+__host__ __device__ constexpr int qy(int i) { return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0); }
+// opposite direction: 1<->3, 2<->4, 5<->7, 6<->8
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5); }
+__host__ __device__ constexpr double qw(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+// E8 stencil position n = 0..23 (0-based): n < 8 the D2Q9 links e_1..e_8,
+// 8..15 the same links doubled, 16..23 the knight moves.  Within every
+// group of four, n and n+2 are opposite.
+__host__ __device__ constexpr int sx(int n)
+{
+    return n < 8 ? qx(n + 1) : n < 16 ? 2 * qx(n - 7)
+         : (n == 16 ? 2 : n == 17 ? -1 : n == 18 ? -2 : n == 19 ? 1 : n == 20 ? 1 : n == 21 ? -2 : n == 22 ? -1 : 2);
+}
+__host__ __device__ constexpr int sy(int n)
+{
+    return n < 8 ? qy(n + 1) : n < 16 ? 2 * qy(n - 7)
+         : (n == 16 ? 1 : n == 17 ? 2 : n == 18 ? -1 : n == 19 ? -2 : n == 20 ? 2 : n == 21 ? 1 : n == 22 ? -2 : -1);
+}
+// Table 1: second-layer position copies first-layer position n-8 (n=9..16),
+// n-12 (17..20) or n-16 (21..24), in 1-based numbering.
+__host__ __device__ constexpr int table1(int n) { return n < 8 ? -1 : n < 16 ? n - 8 : n < 20 ? n - 12 : n - 16; }
+// Eighth-order isotropic weight by |e|^2, normalised to sum W e_x^2 = 1.
+__host__ __device__ constexpr double e8w(int e2)
+{
+    return e2 == 1 ? 4.0 / 21.0 : e2 == 2 ? 4.0 / 45.0 : e2 == 4 ? 1.0 / 60.0 : e2 == 5 ? 2.0 / 315.0 : e2 == 8 ? 1.0 / 5040.0 : 0.0;
+}
+__host__ __device__ constexpr double e8wn(int n) { return e8w(sx(n) * sx(n) + sy(n) * sy(n)); }
+
+// ---------------------------------------------------------------------------
+// Storage traits: raw element type, compute type, sentinel, codec
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;  // NaN -> canonical quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int S> struct Traits;
+
+template <> struct Traits<ST_F64> {
+    using raw_t = double;
+    using C = double;
+    static constexpr bool deviation = false;
+    __device__ static bool sent(raw_t v) { return __double_as_longlong(v) == -1LL; }
+    __device__ static C dec(raw_t v, C) { return v; }
+    __device__ static raw_t enc(C f, C) { return f; }
+    __device__ static raw_t sentinel() { return __longlong_as_double(-1LL); }
+};
+template <> struct Traits<ST_F32> {
+    using raw_t = float;
+    using C = float;
+    static constexpr bool deviation = true;
+    __device__ static bool sent(raw_t v) { return __float_as_uint(v) == 0xffffffffu; }
+    __device__ static C dec(raw_t v, C b) { return v + b; }
+    __device__ static raw_t enc(C f, C b) { return f - b; }
+    __device__ static raw_t sentinel() { return __uint_as_float(0xffffffffu); }
+};
+template <> struct Traits<ST_F16> {
+    using raw_t = uint16_t;
+    using C = float;
+    static constexpr bool deviation = true;
+    __device__ static bool sent(raw_t v) { return v == 0xffffu; }
+    __device__ static C dec(raw_t v, C b) { return (float)__builtin_bit_cast(_Float16, v) + b; }
+    __device__ static raw_t enc(C f, C b) { return __builtin_bit_cast(uint16_t, (_Float16)(f - b)); }
+    __device__ static raw_t sentinel() { return 0xffffu; }
+};
+template <> struct Traits<ST_BF16> {
+    using raw_t = uint16_t;
+    using C = float;
+    static constexpr bool deviation = true;
+    __device__ static bool sent(raw_t v) { return v == 0xffffu; }
+    __device__ static C dec(raw_t v, C b) { return __uint_as_float((uint32_t)v << 16) + b; }
+    __device__ static raw_t enc(C f, C b) { return f32_to_bf16_rne(f - b); }
+    __device__ static raw_t sentinel() { return 0xffffu; }
+};
+
+// Sentinel psi in the LDS tile (same all-ones pattern in the compute type).
+__device__ __forceinline__ bool lds_sent(float v) { return __float_as_uint(v) == 0xffffffffu; }
+__device__ __forceinline__ bool lds_sent(double v) { return __double_as_longlong(v) == -1LL; }
+template <class C> __device__ __forceinline__ C lds_sentinel();
+template <> __device__ __forceinline__ float lds_sentinel<float>() { return __uint_as_float(0xffffffffu); }
+template <> __device__ __forceinline__ double lds_sentinel<double>() { return __longlong_as_double(-1LL); }
+
+template <class C> struct alignas(2 * sizeof(C)) PsiPair {
+    C a, b;  // psi_1, psi_2
+};
+
+// ---------------------------------------------------------------------------
+// Per-run parameters (kernel argument, or a device array for batches)
+// ---------------------------------------------------------------------------
+template <class C> struct KParams {
+    const void *A;  // post-collision set at t-1 (read)
+    void *B;        // post-collision set at t   (written)
+    int nx, ny;
+    unsigned flags;
+    int n_strips, n_segs;
+    int item0;      // first work item of this run in a batch work list
+    long long N;    // nodes = array stride
+    C omega, cforce, half, negGc, Gw1, Gw2, s1, s2, s3, t2, t3, delta;
+    C g[2][2];
+    C base[2][9];   // w_i rho0_k (zero for FP64 storage)
+    // mode outputs
+    double *out_rho1, *out_rho2, *out_ux, *out_uy;
+    double *partials;
+    uint8_t *tab_link, *tab_nw;
+    int32_t *tab_src;
+};
+
+// Position along one axis with its two neighbours, after periodic wrapping;
+// ok* false when the position falls outside a non-periodic domain.
+struct Axis {
+    int c, m, p;
+    bool ok, okm, okp;
+};
+
+__device__ __forceinline__ Axis make_axis(int v, int n, bool periodic)
+{
+    Axis a;
+    if (periodic) {
+        int w = v % n;
+        if (w < 0) w += n;
+        a.c = w;
+        a.m = (w == 0) ? n - 1 : w - 1;
+        a.p = (w == n - 1) ? 0 : w + 1;
+        a.ok = a.okm = a.okp = true;
+    } else {
+        a.c = v;
+        a.m = v - 1;
+        a.p = v + 1;
+        a.ok = v >= 0 && v < n;
+        a.okm = v - 1 >= 0 && v - 1 < n;
+        a.okp = v + 1 >= 0 && v + 1 < n;
+    }
+    return a;
+}
+
+template <class C> struct RowState {
+    C f[2][9];
+    int info;  // bit 8: solid or outside; bits 0-7: bounced-back directions
+};
+
+// Pull the populations f_i(x, t) = f*_i(x - e_i, t-1) of one node, with
+// halfway bounce-back f_i(x, t) = f*_opp(i)(x, t-1) where the source is
+// unavailable (Eq. 1 streaming; bounce-back of Sec. 3.1-3.5).  Computes the
+// densities rho_k (Eq. 3) with the same summation order as the definition.
+template <int S>
+__device__ __forceinline__ void pull_node(const KParams<typename Traits<S>::C> &p, int node,
+                                          const Axis &cx, const Axis &ry,
+                                          RowState<typename Traits<S>::C> &st,
+                                          typename Traits<S>::C &r1, typename Traits<S>::C &r2)
+{
+    using T = Traits<S>;
+    using C = typename T::C;
+    using R = typename T::raw_t;
+    const R *__restrict__ A = (const R *)p.A;
+    const long long N = p.N;
+    const int nx = p.nx;
+    R v[2][9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int ex = qx(i), ey = qy(i);
+        const int scol = ex == 1 ? cx.m : (ex == -1 ? cx.p : cx.c);
+        const bool okx = ex == 1 ? cx.okm : (ex == -1 ? cx.okp : true);
+        const int srow = ey == 1 ? ry.m : (ey == -1 ? ry.p : ry.c);
+        const bool oky = ey == 1 ? ry.okm : (ey == -1 ? ry.okp : true);
+        const bool ok = okx && oky;
+        const int src = ok ? srow * nx + scol : node;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            R val = A[(long long)(k * 9 + i) * N + src];
+            v[k][i] = ok ? val : T::sentinel();
+        }
+    }
+    st.info = 0;
+    if (T::sent(v[0][0])) {  // the node itself is solid
+        st.info = 256;
+        return;
+    }
+    C s1 = 0, s2 = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        st.f[0][i] = T::dec(v[0][i], p.base[0][i]);
+        st.f[1][i] = T::dec(v[1][i], p.base[1][i]);
+        s1 += st.f[0][i];
+        s2 += st.f[1][i];
+    }
+    if (__builtin_isnan(s1 + s2)) {
+        // some source is unavailable (or the state is non-finite): reflect
+        int info = 0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            if (T::sent(v[0][i])) {
+                info |= 1 << (i - 1);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) v[k][i] = A[(long long)(k * 9 + opp(i)) * N + node];
+            }
+        }
+        st.info = info;
+        s1 = 0;
+        s2 = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            st.f[0][i] = T::dec(v[0][i], p.base[0][i]);
+            st.f[1][i] = T::dec(v[1][i], p.base[1][i]);
+            s1 += st.f[0][i];
+            s2 += st.f[1][i];
+        }
+    }
+    r1 = s1;
+    r2 = s2;
+}
+
+// Cohesion sums sum_n W_n e_n Psi_n over the 24 positions, by opposite
+// pairs (n, n+2) in each group of four (Eq. 8 on the E8 stencil).
+// s1 sums psi_1 values, s2 psi_2 values.
+template <class C>
+__device__ __forceinline__ void cohesion_sums(const PsiPair<C> P[24], C &s1x, C &s1y, C &s2x, C &s2y)
+{
+    s1x = 0; s1y = 0; s2x = 0; s2y = 0;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int n = 4 * g + h, o = n + 2;
+            const C cx = (C)(e8wn(n) * sx(n));
+            const C cy = (C)(e8wn(n) * sy(n));
+            const C d1 = P[n].a - P[o].a;
+            const C d2 = P[n].b - P[o].b;
+            if (sx(n) != 0) { s1x += cx * d1; s2x += cx * d2; }
+            if (sy(n) != 0) { s1y += cy * d1; s2y += cy * d2; }
+        }
+    }
+}
+
+// Wall rules for stencil positions (Sec. 2.4, Table 1): an unavailable
+// first-layer position reads `zero` (or `self` under WALLPSI_SELF); an
+// unavailable second-layer position reads whatever its Table 1 partner
+// resolved to (or `zero` under E8_COPY_OFF).  Shared by the step (psi
+// values) and the table export (node indices).
+template <class V>
+__device__ __forceinline__ void apply_wall_rules(V P[24], uint32_t unav, V self, V zero, unsigned flags)
+{
+#pragma unroll
+    for (int n = 0; n < 8; ++n)
+        if ((unav >> n) & 1u) P[n] = (flags & FL_WALLPSI_SELF) ? self : zero;
+#pragma unroll
+    for (int n = 8; n < 24; ++n)
+        if ((unav >> n) & 1u) P[n] = (flags & FL_COPY_OFF) ? zero : P[table1(n)];
+}
+
+// S(x) = sum_n W_n s(x + e_n) e_n from the unavailable-position mask
+// (Eq. 9 on the E8 stencil), by opposite pairs.
+template <class C>
+__device__ __forceinline__ void adhesion_vector(uint32_t unav, C &Sx, C &Sy)
+{
+    Sx = 0;
+    Sy = 0;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int n = 4 * g + h, o = n + 2;
+            const C d = (C)(int)(((unav >> n) & 1u)) - (C)(int)(((unav >> o) & 1u));
+            if (sx(n) != 0) Sx += (C)(e8wn(n) * sx(n)) * d;
+            if (sy(n) != 0) Sy += (C)(e8wn(n) * sy(n)) * d;
+        }
+    }
+}
+
+// Eq. 11: local adhesion parameter of component 1 from rho^e (Eq. 10).
+template <class C>
+__device__ __forceinline__ C local_G(const KParams<C> &p, C re)
+{
+    if (re > p.delta) return p.Gw1;
+    if (re > (C)0) return p.s1 + p.s2 * re + p.s3 * re * re;
+    if (re > -p.delta) return p.s1 + p.t2 * re + p.t3 * re * re;
+    return p.Gw2;
+}
+
+}  // namespace lbm

@@ -1,0 +1,682 @@
+// Kernels of the two-component pseudopotential LBM hot path for gfx950
+// (arXiv 2505.22256).  See lbm_device.hpp for the data layout.
+//
+// Step kernel: pull scheme.  The buffer read holds the post-collision set
+// f*(t-1); pulling gives f(x, t), from which the densities at time t, the
+// forces (Eq. 8-9, 11) and the collision (Eq. 1-2, 6-7) follow, and f*(t)
+// is written to the other buffer.  The cohesion at x needs psi = rho(t) at
+// the 24 E8 positions around x, so each workgroup also pulls a 2-node halo
+// of rows and columns and keeps psi in an LDS ring of rows.
+//
+// Work decomposition: a workgroup of BLOCK threads owns a strip of at most
+// BLOCK-4 columns (one thread per column plus two halo columns on each
+// side) and marches down a segment of rows.  Each iteration pulls row y+2
+// into registers and the LDS ring, synchronises once, and finishes row y,
+// whose populations were pulled two iterations earlier and stayed in
+// registers.  HBM traffic is one read and one write of every population;
+// halo re-reads hit L2.  Work items are dealt to the 8 XCDs in contiguous
+// chunks so that neighbouring segments share an L2.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+__device__ __forceinline__ int ring_slot(int r) { return (r + 8) & 7; }
+
+// Reduction accumulators of one thread (FP64).
+struct RedAcc {
+    double m1 = 0, m2 = 0, px = 0, py = 0, umax = 0, rmin = __builtin_inf(), rmax = -__builtin_inf(), bad = 0;
+};
+
+template <int S, int BLOCK>
+__device__ __forceinline__ void pull_row(const KParams<typename Traits<S>::C> &p, const Axis &cx,
+                                         bool col_ok, int r,
+                                         PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
+                                         RowState<typename Traits<S>::C> &st)
+{
+    using C = typename Traits<S>::C;
+    const Axis ry = make_axis(r, p.ny, p.flags & FL_PERIODIC_Y);
+    PsiPair<C> ps;
+    ps.a = lds_sentinel<C>();
+    ps.b = lds_sentinel<C>();
+    st.info = 256;
+    if (col_ok && ry.ok) {
+        const int node = ry.c * p.nx + cx.c;
+        C r1, r2;
+        pull_node<S>(p, node, cx, ry, st, r1, r2);
+        if (!(st.info & 256)) {
+            ps.a = r1;
+            ps.b = r2;
+        }
+    }
+    ring[ring_slot(r)][threadIdx.x] = ps;
+}
+
+// Finish fluid-or-solid node (x, y) of an interior column: stencil, forces,
+// velocity, collision and the selected outputs.
+template <int S, int BLOCK, int MODE>
+__device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C> &p, const Axis &cx, int y,
+                                            const RowState<typename Traits<S>::C> &st,
+                                            PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
+{
+    using T = Traits<S>;
+    using C = typename T::C;
+    using R = typename T::raw_t;
+    const int node = y * p.nx + cx.c;
+    const int tid = threadIdx.x;
+
+    if (st.info & 256) {  // solid node
+        if (MODE & M_FIELDS) {
+            p.out_rho1[node] = 0.0;
+            p.out_rho2[node] = 0.0;
+            p.out_ux[node] = 0.0;
+            p.out_uy[node] = 0.0;
+        }
+        if (MODE & M_TABLES) {
+            p.tab_link[node] = 0;
+            p.tab_nw[node] = 0;
+        }
+        return;
+    }
+
+    const PsiPair<C> ctr = ring[ring_slot(y)][tid];
+    const C r1 = ctr.a, r2 = ctr.b;
+
+    // first moments j_k = sum_i f_i e_i (Eq. 4), definition order
+    const C(&f)[2][9] = st.f;
+    C jx[2], jy[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        C ax = f[k][1];
+        ax -= f[k][3];
+        ax += f[k][5];
+        ax -= f[k][6];
+        ax -= f[k][7];
+        ax += f[k][8];
+        C ay = f[k][2];
+        ay -= f[k][4];
+        ay += f[k][5];
+        ay += f[k][6];
+        ay -= f[k][7];
+        ay -= f[k][8];
+        jx[k] = ax;
+        jy[k] = ay;
+    }
+
+    // E8 stencil of psi around x
+    PsiPair<C> P[24];
+#pragma unroll
+    for (int n = 0; n < 24; ++n) P[n] = ring[ring_slot(y + sy(n))][tid + sx(n)];
+
+    C s1x, s1y, s2x, s2y;
+    cohesion_sums<C>(P, s1x, s1y, s2x, s2y);
+    uint32_t unav = 0;
+    C Sx = 0, Sy = 0;
+    const bool near = __builtin_isnan(s1x + s1y + s2x + s2y);
+    if (near || (MODE & M_TABLES)) {
+#pragma unroll
+        for (int n = 0; n < 24; ++n) unav |= (uint32_t)lds_sent(P[n].a) << n;
+    }
+    if (near) {
+        PsiPair<C> self, zero;
+        self.a = r1;
+        self.b = r2;
+        zero.a = 0;
+        zero.b = 0;
+        apply_wall_rules<PsiPair<C>>(P, unav, self, zero, p.flags);
+        cohesion_sums<C>(P, s1x, s1y, s2x, s2y);
+        adhesion_vector<C>(unav, Sx, Sy);
+    }
+
+    if (MODE & M_TABLES) {
+        p.tab_link[node] = (uint8_t)(st.info & 255);
+        p.tab_nw[node] = unav ? 1 : 0;
+        if (unav) {
+            int idx[24];
+#pragma unroll
+            for (int n = 0; n < 24; ++n) {
+                const Axis ax = make_axis(cx.c + sx(n), p.nx, p.flags & FL_PERIODIC_X);
+                const Axis ay = make_axis(y + sy(n), p.ny, p.flags & FL_PERIODIC_Y);
+                idx[n] = (ax.ok && ay.ok) ? ay.c * p.nx + ax.c : -1;
+            }
+            apply_wall_rules<int>(idx, unav, node, -1, p.flags);
+#pragma unroll
+            for (int n = 0; n < 24; ++n) p.tab_src[(long long)node * 24 + n] = idx[n];
+        }
+        if (!(MODE & (M_STORE | M_FIELDS | M_REDUCE))) return;
+    }
+
+    // forces: cohesion (Eq. 8) + adhesion (Eq. 9, 11) + body force
+    C Fx[2], Fy[2];
+    Fx[0] = (p.negGc * r1) * s2x;
+    Fy[0] = (p.negGc * r1) * s2y;
+    Fx[1] = (p.negGc * r2) * s1x;
+    Fy[1] = (p.negGc * r2) * s1y;
+    if (near) {
+        C G1 = p.Gw1;
+        if (!(p.flags & FL_ORIGINAL)) G1 = local_G<C>(p, (r1 - r2) / (r1 + r2));
+        const C a1 = -G1 * r1, a2 = -p.Gw2 * r2;
+        Fx[0] += a1 * Sx;
+        Fy[0] += a1 * Sy;
+        Fx[1] += a2 * Sx;
+        Fy[1] += a2 * Sy;
+    }
+    const bool fdens = p.flags & FL_FORCE_DENSITY;
+    Fx[0] += (fdens ? (C)1 : r1) * p.g[0][0];
+    Fy[0] += (fdens ? (C)1 : r1) * p.g[0][1];
+    Fx[1] += (fdens ? (C)1 : r2) * p.g[1][0];
+    Fy[1] += (fdens ? (C)1 : r2) * p.g[1][1];
+
+    // common velocity (Eq. 5 with the half-force shift of Guo's scheme)
+    const C rt = r1 + r2;
+    const C ux = ((jx[0] + p.half * Fx[0]) + (jx[1] + p.half * Fx[1])) / rt;
+    const C uy = ((jy[0] + p.half * Fy[0]) + (jy[1] + p.half * Fy[1])) / rt;
+
+    if (MODE & M_FIELDS) {
+        p.out_rho1[node] = (double)r1;
+        p.out_rho2[node] = (double)r2;
+        p.out_ux[node] = (double)ux;
+        p.out_uy[node] = (double)uy;
+    }
+    if (MODE & M_REDUCE) {
+        const double d1 = r1, d2 = r2, dux = ux, duy = uy;
+        if (!__builtin_isfinite(d1) || !__builtin_isfinite(d2) || !__builtin_isfinite(dux) ||
+            !__builtin_isfinite(duy)) {
+            acc.bad += 1.0;
+        } else {
+            const double drt = d1 + d2;
+            acc.m1 += d1;
+            acc.m2 += d2;
+            acc.px += drt * dux;
+            acc.py += drt * duy;
+            const double um = __builtin_sqrt(dux * dux + duy * duy);
+            acc.umax = um > acc.umax ? um : acc.umax;
+            acc.rmin = d1 < acc.rmin ? d1 : acc.rmin;
+            acc.rmax = d1 > acc.rmax ? d1 : acc.rmax;
+        }
+    }
+
+    if (MODE & M_STORE) {
+        // BGK with Guo forcing (Eq. 1, 2, 6, 7):
+        // f* = f + omega (f^eq - f) + (1 - omega/2) F_i,
+        // f^eq = w rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u],
+        // F_i = w [3 (e.F - u.F) + 9 (e.u)(e.F)].
+        R *__restrict__ B = (R *)p.B;
+        const C a0 = (C)1 - (C)1.5 * (ux * ux + uy * uy);
+        const C rho[2] = {r1, r2};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const C uF = ux * Fx[k] + uy * Fy[k];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const C w = (C)qw(i);
+                const int ex = qx(i), ey = qy(i);
+                const C eu = (C)ex * ux + (C)ey * uy;
+                const C eF = (C)ex * Fx[k] + (C)ey * Fy[k];
+                const C feq = w * rho[k] * (a0 + eu * ((C)3 + (C)4.5 * eu));
+                const C Fi = w * ((C)3 * (eF - uF) + (C)9 * eu * eF);
+                const C fs = f[k][i] + p.omega * (feq - f[k][i]) + p.cforce * Fi;
+                B[(long long)(k * 9 + i) * p.N + node] = T::enc(fs, p.base[k][i]);
+            }
+        }
+    }
+}
+
+// Block-wide deterministic reduction of the 8 accumulators; thread 0 writes
+// the workgroup's partial record.
+template <int BLOCK>
+__device__ void block_reduce_write(RedAcc acc, double *out)
+{
+    __shared__ double red[8][BLOCK];
+    const int t = threadIdx.x;
+    red[0][t] = acc.m1;
+    red[1][t] = acc.m2;
+    red[2][t] = acc.px;
+    red[3][t] = acc.py;
+    red[4][t] = acc.umax;
+    red[5][t] = acc.rmin;
+    red[6][t] = acc.rmax;
+    red[7][t] = acc.bad;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            red[0][t] += red[0][t + s];
+            red[1][t] += red[1][t + s];
+            red[2][t] += red[2][t + s];
+            red[3][t] += red[3][t + s];
+            red[4][t] = red[4][t] > red[4][t + s] ? red[4][t] : red[4][t + s];
+            red[5][t] = red[5][t] < red[5][t + s] ? red[5][t] : red[5][t + s];
+            red[6][t] = red[6][t] > red[6][t + s] ? red[6][t] : red[6][t + s];
+            red[7][t] += red[7][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int q = 0; q < 8; ++q) out[q] = red[q][0];
+}
+
+// Process one (strip, segment) work item of a run.
+template <int S, int BLOCK, int MODE>
+__device__ __forceinline__ void process_item(const KParams<typename Traits<S>::C> &p, int strip, int seg,
+                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
+{
+    using C = typename Traits<S>::C;
+    const int tid = threadIdx.x;
+    const int x0 = (int)(((long long)strip * p.nx) / p.n_strips);
+    const int x1 = (int)(((long long)(strip + 1) * p.nx) / p.n_strips);
+    const int y0 = (int)(((long long)seg * p.ny) / p.n_segs);
+    const int y1 = (int)(((long long)(seg + 1) * p.ny) / p.n_segs);
+    const int w = x1 - x0;
+    const bool active = tid < w + 4;
+    const bool interior = tid >= 2 && tid < w + 2;
+    const Axis cx = make_axis(x0 - 2 + tid, p.nx, p.flags & FL_PERIODIC_X);
+    const bool col_ok = active && cx.ok;
+
+    RowState<C> ra, rb, rc;
+    pull_row<S, BLOCK>(p, cx, col_ok, y0 - 2, ring, ra);
+    pull_row<S, BLOCK>(p, cx, col_ok, y0 - 1, ring, ra);
+    pull_row<S, BLOCK>(p, cx, col_ok, y0, ring, ra);
+    pull_row<S, BLOCK>(p, cx, col_ok, y0 + 1, ring, rb);
+    int y = y0;
+    for (;;) {
+        if (y >= y1) break;
+        pull_row<S, BLOCK>(p, cx, col_ok, y + 2, ring, rc);
+        __syncthreads();
+        if (interior) finish_node<S, BLOCK, MODE>(p, cx, y, ra, ring, acc);
+        ++y;
+        if (y >= y1) break;
+        pull_row<S, BLOCK>(p, cx, col_ok, y + 2, ring, ra);
+        __syncthreads();
+        if (interior) finish_node<S, BLOCK, MODE>(p, cx, y, rb, ring, acc);
+        ++y;
+        if (y >= y1) break;
+        pull_row<S, BLOCK>(p, cx, col_ok, y + 2, ring, rb);
+        __syncthreads();
+        if (interior) finish_node<S, BLOCK, MODE>(p, cx, y, rc, ring, acc);
+        ++y;
+    }
+}
+
+// One time step (or one field/diagnostic/table pass) of a single run.
+// Grid: 8 * per_xcd workgroups; workgroup b takes item (b % 8) * per_xcd + b / 8.
+template <int S, int BLOCK, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_step(const KParams<typename Traits<S>::C> p, int per_xcd)
+{
+    using C = typename Traits<S>::C;
+    __shared__ PsiPair<C> ring[8][BLOCK];
+    const int b = blockIdx.x;
+    const int item = (b & 7) * per_xcd + (b >> 3);
+    RedAcc acc;
+    if (item < p.n_strips * p.n_segs) {
+        const int strip = item / p.n_segs;
+        process_item<S, BLOCK, MODE>(p, strip, item - strip * p.n_segs, ring, acc);
+    }
+    if (MODE & M_REDUCE) {
+        __syncthreads();
+        block_reduce_write<BLOCK>(acc, p.partials + (long long)b * 8);
+    }
+}
+
+// Batched step: the work list concatenates the (strip, segment) items of
+// all runs; run r owns items [item0_r, item0_r + strips_r * segs_r).
+template <int S, int BLOCK, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+k_step_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns, int n_items, int per_xcd, int flip)
+{
+    using C = typename Traits<S>::C;
+    __shared__ PsiPair<C> ring[8][BLOCK];
+    const int b = blockIdx.x;
+    const int item = (b & 7) * per_xcd + (b >> 3);
+    if (item >= n_items) return;
+    // binary search for the run owning this item
+    int lo = 0, hi = nruns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (runs[mid].item0 <= item) lo = mid; else hi = mid - 1;
+    }
+    KParams<C> p = runs[lo];
+    if (flip) {
+        const void *t = p.A;
+        p.A = p.B;
+        p.B = (void *)t;
+    }
+    const int local = item - p.item0;
+    const int strip = local / p.n_segs;
+    RedAcc acc;
+    process_item<S, BLOCK, MODE>(p, strip, local - strip * p.n_segs, ring, acc);
+}
+
+// Finalise diagnostics: deterministic compensated (Neumaier) sums over the
+// workgroup partials in a fixed order; one workgroup of 256 threads.
+static __global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__ partials, int nparts, double *out)
+{
+    __shared__ double s[5][256], cmp[5][256], mx[3][256];
+    const int t = threadIdx.x;
+    double sum[5] = {0, 0, 0, 0, 0}, c[5] = {0, 0, 0, 0, 0};
+    double umax = 0, rmin = __builtin_inf(), rmax = -__builtin_inf();
+    const int idx[5] = {0, 1, 2, 3, 7};
+    for (int j = t; j < nparts; j += 256) {
+        const double *q = partials + (long long)j * 8;
+        for (int a = 0; a < 5; ++a) {
+            const double v = q[idx[a]], tt = sum[a] + v;
+            c[a] += (__builtin_fabs(sum[a]) >= __builtin_fabs(v)) ? (sum[a] - tt) + v : (v - tt) + sum[a];
+            sum[a] = tt;
+        }
+        umax = q[4] > umax ? q[4] : umax;
+        rmin = q[5] < rmin ? q[5] : rmin;
+        rmax = q[6] > rmax ? q[6] : rmax;
+    }
+    for (int a = 0; a < 5; ++a) {
+        s[a][t] = sum[a];
+        cmp[a][t] = c[a];
+    }
+    mx[0][t] = umax;
+    mx[1][t] = rmin;
+    mx[2][t] = rmax;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            for (int a = 0; a < 5; ++a) {
+                const double x = s[a][t], v = s[a][t + h], tt = x + v;
+                cmp[a][t] += cmp[a][t + h] + ((__builtin_fabs(x) >= __builtin_fabs(v)) ? (x - tt) + v : (v - tt) + x);
+                s[a][t] = tt;
+            }
+            mx[0][t] = mx[0][t] > mx[0][t + h] ? mx[0][t] : mx[0][t + h];
+            mx[1][t] = mx[1][t] < mx[1][t + h] ? mx[1][t] : mx[1][t + h];
+            mx[2][t] = mx[2][t] > mx[2][t + h] ? mx[2][t] : mx[2][t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = s[0][0] + cmp[0][0];
+        out[1] = s[1][0] + cmp[1][0];
+        out[2] = s[2][0] + cmp[2][0];
+        out[3] = s[3][0] + cmp[3][0];
+        out[4] = mx[0][0];
+        out[5] = mx[1][0];
+        out[6] = mx[2][0];
+        out[7] = s[4][0] + cmp[4][0];
+    }
+}
+
+// Post-collision set whose streaming gives the pre-collision set f(t):
+// slot (z, j) is pulled by z + e_j when that position is available, else by
+// z itself as the bounce-back of direction opp(j).  So
+// f*_j(z) = f_j(z + e_j) or f_opp(j)(z).  Source f is FP64 [2][9][N]; when
+// `rho` is given instead, f_i = w_i rho_k (equilibrium at rest).
+template <int S>
+__global__ void __launch_bounds__(256)
+k_inverse_stream(const KParams<typename Traits<S>::C> p, const uint8_t *__restrict__ solid,
+                 const double *__restrict__ fsrc, const double *__restrict__ rho)
+{
+    using T = Traits<S>;
+    using R = typename T::raw_t;
+    const long long z = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (z >= p.N) return;
+    R *__restrict__ A = (R *)p.B;
+    if (solid[z]) return;  // slots stay at the sentinel
+    const int x = (int)(z % p.nx), y = (int)(z / p.nx);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const Axis ax = make_axis(x + qx(j), p.nx, p.flags & FL_PERIODIC_X);
+        const Axis ay = make_axis(y + qy(j), p.ny, p.flags & FL_PERIODIC_Y);
+        const long long nb = (long long)ay.c * p.nx + ax.c;
+        const bool avail = ax.ok && ay.ok && !solid[nb];
+        for (int k = 0; k < 2; ++k) {
+            double v;
+            if (rho) {
+                v = qw(j) * rho[(long long)k * p.N + (avail ? nb : z)];
+            } else {
+                v = avail ? fsrc[(long long)(k * 9 + j) * p.N + nb] : fsrc[(long long)(k * 9 + opp(j)) * p.N + z];
+            }
+            A[(long long)(k * 9 + j) * p.N + z] = T::enc((typename T::C)v, p.base[k][j]);
+        }
+    }
+}
+
+// Pre-collision populations f(x, t) as FP64 [2][9][N] (solid -> 0), by the
+// same pull as the step kernel.
+template <int S>
+__global__ void __launch_bounds__(256) k_pull_populations(const KParams<typename Traits<S>::C> p, double *__restrict__ out)
+{
+    using C = typename Traits<S>::C;
+    const long long z = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (z >= p.N) return;
+    const int x = (int)(z % p.nx), y = (int)(z / p.nx);
+    const Axis cx = make_axis(x, p.nx, p.flags & FL_PERIODIC_X);
+    const Axis ry = make_axis(y, p.ny, p.flags & FL_PERIODIC_Y);
+    RowState<C> st;
+    C r1, r2;
+    pull_node<S>(p, (int)z, cx, ry, st, r1, r2);
+    const bool solid = st.info & 256;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[(long long)(k * 9 + i) * p.N + z] = solid ? 0.0 : (double)st.f[k][i];
+}
+
+// Same, for the w x h window at (x0, y0) (periodic wrap), out [2][9][h][w].
+template <int S>
+__global__ void __launch_bounds__(256)
+k_pull_window(const KParams<typename Traits<S>::C> p, int x0, int y0, int w, int h, double *__restrict__ out)
+{
+    using C = typename Traits<S>::C;
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long M = (long long)w * h;
+    if (q >= M) return;
+    const int wx = (int)(q % w), wy = (int)(q / w);
+    const Axis cx = make_axis(x0 + wx, p.nx, p.flags & FL_PERIODIC_X);
+    const Axis ry = make_axis(y0 + wy, p.ny, p.flags & FL_PERIODIC_Y);
+    RowState<C> st;
+    C r1, r2;
+    pull_node<S>(p, ry.c * p.nx + cx.c, cx, ry, st, r1, r2);
+    const bool solid = st.info & 256;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[(long long)(k * 9 + i) * M + q] = solid ? 0.0 : (double)st.f[k][i];
+}
+
+// ---------------------------------------------------------------------------
+// Contact angle (FP64): interface points of rho^e = 0 along links, algebraic
+// circle fit, Gauss-Newton refinement, angle with the wall.
+// ---------------------------------------------------------------------------
+struct WallDesc {
+    int kind;
+    double w0, w1, w2;
+};
+
+__device__ __forceinline__ bool interface_point(int nx, int ny, const double *r1, const double *r2,
+                                                const uint8_t *solid, const WallDesc &wd, long long a,
+                                                int dir, double &qx_, double &qy_)
+{
+    const int x = (int)(a % nx), y = (int)(a / nx);
+    const int x2 = x + (dir == 0), y2 = y + (dir == 1);
+    if (x2 >= nx || y2 >= ny) return false;
+    const long long b = (long long)y2 * nx + x2;
+    if (solid[a] || solid[b]) return false;
+    const double ra = (r1[a] - r2[a]) / (r1[a] + r2[a]);
+    const double rb = (r1[b] - r2[b]) / (r1[b] + r2[b]);
+    if ((ra > 0.0) == (rb > 0.0)) return false;
+    const double t = ra / (ra - rb);
+    qx_ = x + t * (x2 - x);
+    qy_ = y + t * (y2 - y);
+    double dist;
+    if (wd.kind == 0) {
+        dist = qy_ - wd.w0;
+    } else {
+        const double dx = qx_ - wd.w0, dy = qy_ - wd.w1;
+        dist = __builtin_sqrt(dx * dx + dy * dy) - wd.w2;
+    }
+    return dist >= 3.0;
+}
+
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double (*sh)[256])
+{
+    const int t = threadIdx.x;
+    __syncthreads();
+    for (int q = 0; q < NV; ++q) sh[q][t] = v[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int q = 0; q < NV; ++q) sh[q][t] += sh[q][t + h];
+        __syncthreads();
+    }
+    for (int q = 0; q < NV; ++q) v[q] = sh[q][0];
+}
+
+static __device__ bool solve3(double A[3][3], double b[3], double x[3])
+{
+    double M[3][4];
+    for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) M[r][q] = A[r][q];
+        M[r][3] = b[r];
+    }
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (__builtin_fabs(M[r][col]) > __builtin_fabs(M[piv][col])) piv = r;
+        if (M[piv][col] == 0.0) return false;
+        if (piv != col)
+            for (int q = 0; q < 4; ++q) {
+                const double tmp = M[col][q];
+                M[col][q] = M[piv][q];
+                M[piv][q] = tmp;
+            }
+        for (int r = col + 1; r < 3; ++r) {
+            const double fct = M[r][col] / M[col][col];
+            for (int q = col; q < 4; ++q) M[r][q] -= fct * M[col][q];
+        }
+    }
+    for (int r = 2; r >= 0; --r) {
+        double s = M[r][3];
+        for (int q = r + 1; q < 3; ++q) s -= M[r][q] * x[q];
+        x[r] = s / M[r][r];
+    }
+    return true;
+}
+
+// One workgroup per run.  out[run*6]: theta (deg), centre x, centre y,
+// radius, number of points, status (0 ok, 1 too few points, 2 fit failed).
+static __global__ void __launch_bounds__(256)
+k_contact_angle(const int *__restrict__ dims /* nx, ny per run */, const long long *__restrict__ offs,
+                const double *__restrict__ rho1, const double *__restrict__ rho2,
+                const uint8_t *__restrict__ solid, const WallDesc *__restrict__ walls, double *out)
+{
+    __shared__ double sh[9][256];
+    __shared__ double params[4];
+    __shared__ int flag;
+    const int run = blockIdx.x, t = threadIdx.x;
+    const int nx = dims[2 * run], ny = dims[2 * run + 1];
+    const long long off = offs[run];
+    const double *r1 = rho1 + off, *r2 = rho2 + off;
+    const uint8_t *sd = solid + off;
+    const WallDesc wd = walls[run];
+    const long long N = (long long)nx * ny;
+
+    // pass 1: count and mean
+    double m[3] = {0, 0, 0};
+    for (long long a = t; a < N; a += 256)
+        for (int dir = 0; dir < 2; ++dir) {
+            double qx_, qy_;
+            if (interface_point(nx, ny, r1, r2, sd, wd, a, dir, qx_, qy_)) {
+                m[0] += 1.0;
+                m[1] += qx_;
+                m[2] += qy_;
+            }
+        }
+    block_sum<3>(m, sh);
+    double *o = out + (long long)run * 6;
+    if (m[0] < 3.0) {
+        if (t == 0) {
+            o[0] = 0; o[1] = 0; o[2] = 0; o[3] = 0; o[4] = m[0]; o[5] = 1;
+        }
+        return;
+    }
+    const double mx = m[1] / m[0], my = m[2] / m[0];
+    // pass 2: algebraic fit on centred points
+    double k9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long a = t; a < N; a += 256)
+        for (int dir = 0; dir < 2; ++dir) {
+            double qx_, qy_;
+            if (interface_point(nx, ny, r1, r2, sd, wd, a, dir, qx_, qy_)) {
+                const double u = qx_ - mx, v = qy_ - my, z = u * u + v * v;
+                k9[0] += u * u; k9[1] += u * v; k9[2] += u;
+                k9[3] += v * v; k9[4] += v;
+                k9[5] += 1.0;
+                k9[6] -= u * z; k9[7] -= v * z; k9[8] -= z;
+            }
+        }
+    block_sum<9>(k9, sh);
+    if (t == 0) {
+        double A[3][3] = {{k9[0], k9[1], k9[2]}, {k9[1], k9[3], k9[4]}, {k9[2], k9[4], k9[5]}};
+        double bb[3] = {k9[6], k9[7], k9[8]}, DEF[3];
+        flag = 0;
+        if (!solve3(A, bb, DEF)) flag = 2;
+        const double r2v = DEF[0] * DEF[0] / 4.0 + DEF[1] * DEF[1] / 4.0 - DEF[2];
+        if (!(r2v > 0.0)) flag = 2;
+        params[0] = mx - DEF[0] / 2.0;
+        params[1] = my - DEF[1] / 2.0;
+        params[2] = flag ? 0.0 : __builtin_sqrt(r2v);
+    }
+    __syncthreads();
+    if (flag) {
+        if (t == 0) {
+            o[0] = 0; o[1] = 0; o[2] = 0; o[3] = 0; o[4] = m[0]; o[5] = 2;
+        }
+        return;
+    }
+    // Gauss-Newton on the geometric distance
+    for (int it = 0; it < 100; ++it) {
+        const double a0 = params[0], b0 = params[1], rr = params[2];
+        double g9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (long long a = t; a < N; a += 256)
+            for (int dir = 0; dir < 2; ++dir) {
+                double qx_, qy_;
+                if (interface_point(nx, ny, r1, r2, sd, wd, a, dir, qx_, qy_)) {
+                    const double dx = qx_ - a0, dy = qy_ - b0;
+                    const double d = __builtin_sqrt(dx * dx + dy * dy);
+                    if (d == 0.0) continue;
+                    const double J0 = -dx / d, J1 = -dy / d, J2 = -1.0, res = d - rr;
+                    g9[0] += J0 * J0; g9[1] += J0 * J1; g9[2] += J0 * J2;
+                    g9[3] += J1 * J1; g9[4] += J1 * J2; g9[5] += J2 * J2;
+                    g9[6] -= J0 * res; g9[7] -= J1 * res; g9[8] -= J2 * res;
+                }
+            }
+        block_sum<9>(g9, sh);
+        if (t == 0) {
+            double A[3][3] = {{g9[0], g9[1], g9[2]}, {g9[1], g9[3], g9[4]}, {g9[2], g9[4], g9[5]}};
+            double bb[3] = {g9[6], g9[7], g9[8]}, dl[3];
+            flag = 1;  // stop
+            if (solve3(A, bb, dl)) {
+                params[0] += dl[0];
+                params[1] += dl[1];
+                params[2] += dl[2];
+                const double step = __builtin_fabs(dl[0]) + __builtin_fabs(dl[1]) + __builtin_fabs(dl[2]);
+                flag = step <= 1e-13 * (1.0 + __builtin_fabs(params[2])) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (flag) break;
+    }
+    if (t == 0) {
+        double cth;
+        if (wd.kind == 0) {
+            cth = -(params[1] - wd.w0) / params[2];
+        } else {
+            const double dx = params[0] - wd.w0, dy = params[1] - wd.w1;
+            cth = (wd.w2 * wd.w2 + params[2] * params[2] - (dx * dx + dy * dy)) / (2.0 * wd.w2 * params[2]);
+        }
+        cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
+        o[0] = acos(cth) * (180.0 / 3.14159265358979323846);
+        o[1] = params[0];
+        o[2] = params[1];
+        o[3] = params[2];
+        o[4] = m[0];
+        o[5] = 0;
+    }
+}
+
+}  // namespace lbm

@@ -24,3 +24,20 @@ def oracle_mod():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name every GPU case on the real stderr before it runs, so that a run
+    that ends abruptly still shows which case was on the device."""
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write(f"[gpu case] {request.node.nodeid}\n")
+        sys.__stderr__.flush()
+    yield
+
+
+@pytest.fixture(scope="session")
+def lbm_mod():
+    from paper_2505_22256_amd import lbm
+    lbm.load_library()
+    return lbm
