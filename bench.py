@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the two-component pseudopotential LBM hot path.
+
+One step = one lattice time step of the fused kernel (pull streaming with
+bounce-back, densities, E8 cohesion with the second-layer copy, local
+adhesion, body force, BGK-Guo collision, store), with the FP64 diagnostics
+fused into every 100th step.  Workload: the 16384 x 2048 walled microchannel
+with 64 square constrictions (side 128), two components as parallel streams,
+G_c = 0.9, G_ads = 0.15, tau = 1, body acceleration 2e-6 on both, FP32
+deviation storage.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: MLUPS (fluid-node updates per second, both components
+per update), the HBM roofline fraction of the step kernel (algorithmic
+bytes: 2 x 9 populations x (read + write) + 1 byte of geometry per fluid
+update), the FP64 CPU oracle on a bounded sample as a baseline, and the
+contact-angle error of the reduced-precision storages on the flat-wall
+droplet against the FP64 path.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2505_22256_amd import lbm, workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "2-comp D2Q9 MLUPS, % of HBM roofline, contact-angle error vs FP64 oracle"
+STORAGES = {"f64": lbm.F64, "f32": lbm.F32, "f16": lbm.F16, "bf16": lbm.BF16}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_constrictions.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_api.hip"):
+        with open(os.path.join(ROOT, "paper_2505_22256_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage_name: str, n_fluid: int):
+    """HBM bytes per step launch from the committed rocprofv3 counter runs,
+    only while they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(storage_name)
+    if not ent or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, seconds: float = 12.0):
+    """FP64 oracle on a bounded sample of the same workload: the first 1024
+    columns of the channel (periodic in x), stepped until `seconds` pass."""
+    import oracle  # the oracle: CPU baseline only
+    oracle.build(force=False)
+    w = 1024
+    o = oracle.Oracle(w, wl.ny, wl.flags)
+    o.set_geometry(wl.solid[:, :w])
+    o.set_params(wl.G_c, wl.G_ads, wl.tau)
+    o.set_body_accel(*wl.accel)
+    o.init_fields(wl.rho1[:, :w], wl.rho2[:, :w])
+    o.step(1)
+    nf = int(w * wl.ny - wl.solid[:, :w].sum())
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(2)
+        steps += 2
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": round(nf * steps / el / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"constriction channel columns 0..{w - 1} x {wl.ny} rows (periodic in x), "
+                      f"{steps} FP64 steps, {el:.1f} s"}
+
+
+def precision_check(steps: int = 5000):
+    """Contact angle of the flat-wall droplet (100x50, lambda = 13/9) after
+    `steps` steps per storage, against the FP64 path (which agrees with the
+    FP64 oracle to 1e-12)."""
+    wl = W.flat_drop()
+    cases = [("f64", lbm.F64, 0), ("f32", lbm.F32, 0), ("f16", lbm.F16, 0),
+             ("f16_sr", lbm.F16, lbm.ROUND_STOCHASTIC), ("bf16", lbm.BF16, 0),
+             ("bf16_sr", lbm.BF16, lbm.ROUND_STOCHASTIC)]
+    th = {}
+    for name, st, fl in cases:
+        g = lbm.lattice_from_workload(wl, st, fl)
+        g.step(steps)
+        try:
+            th[name] = g.contact_angle(wl.wall_kind, wl.wall)
+        except lbm.LbmError:
+            th[name] = float("nan")
+        g.close()
+    ref = th["f64"]
+    return {"workload": f"flat-wall droplet 100x50, {steps} steps", "theta_f64_deg": round(ref, 4),
+            "theta_err_deg": {k: (round(abs(v - ref), 4) if math.isfinite(v) else None)
+                              for k, v in th.items() if k != "f64"}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
+    ap.add_argument("--stochastic", action="store_true", help="stochastic rounding (f16/bf16)")
+    ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--tile", default="auto", help="auto or BLOCK,ROWS[,SCHED]")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (read BYTES, write BYTES) five "
+                         "times, to scale HBM byte counters against a known traffic")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 5}))
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
+              "decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch  # device streams and events only
+
+    wl = W.constrictions()
+    storage = STORAGES[args.storage]
+    flags = lbm.ROUND_STOCHASTIC if args.stochastic else 0
+    stream = torch.cuda.Stream()
+    lat = lbm.lattice_from_workload(wl, storage, flags)
+    lat.set_stream(stream.cuda_stream)
+    if args.tile == "auto":
+        block, rows, sched = lat.autotune(3)
+    else:
+        vals = [int(v) for v in args.tile.split(",")]
+        block, rows, sched = vals[0], vals[1], (vals[2] if len(vals) > 2 else 0)
+        lat.set_tile(block, rows, sched)
+    lat.set_diag_interval(args.diag_every)
+    n_fluid = lat.fluid_nodes
+    bpu = lat.bytes_per_update
+
+    with torch.cuda.stream(stream):
+        lat.step(args.warmup)
+        lat.synchronize()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        lat.step(args.steps)
+        ev1.record(stream)
+        ev1.synchronize()
+        torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    diag, t_diag = lat.get_diag() if args.diag_every > 0 else (None, None)
+    ms_step = ms / args.steps
+    mlups = n_fluid * args.steps / (ms * 1e-3) / 1e6
+    achieved = bpu * n_fluid / (ms_step * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage, n_fluid)
+    lat.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if storage == lbm.F64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"constrictions {wl.nx}x{wl.ny} (64 squares of side 128, seed 355), "
+                               f"G_c=0.9 G_ads=0.15 tau=1 g=2e-6, {args.storage} storage"
+                               + (" stochastic rounding" if args.stochastic else ""),
+                   "nx": wl.nx, "ny": wl.ny, "fluid_nodes": n_fluid, "storage": args.storage,
+                   "tile": {"block": block, "seg_rows": rows, "sched": sched},
+                   "diag_every": args.diag_every},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_update": bpu},
+    }
+    if diag is not None:
+        out["diagnostics"] = {"t": t_diag, "mass1": diag[0], "mass2": diag[1], "max_u": diag[4],
+                              "nonfinite_nodes": int(diag[7])}
+    if not args.no_accuracy:
+        out["accuracy"] = precision_check()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -67,7 +67,13 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
  *   WALLPSI_SELF     unavailable first-layer positions read psi(x) instead of 0;
  *   VEL_LITERAL      u^eq = sum_k j_k / sum_k rho_k (Eq. 4-5 without the
  *                    half-force shift of Guo's scheme);
- *   FORCE_DENSITY    body force g_k per unit volume instead of rho_k g_k. */
+ *   FORCE_DENSITY    body force g_k per unit volume instead of rho_k g_k.
+ * ROUND_STOCHASTIC (F16 and BF16 storage only; ignored otherwise) rounds the
+ * stored deviation up or down with probability proportional to the
+ * distance, from a counter-based hash of (node, component, direction,
+ * step): unbiased, reproducible and independent of the tiling.  The default
+ * is round-to-nearest-even, whose error repeats every step in a steady
+ * state and accumulates (mass drift). */
 enum {
     LBM_PERIODIC_X = 1,
     LBM_PERIODIC_Y = 2,
@@ -75,8 +81,12 @@ enum {
     LBM_E8_COPY_OFF = 8,
     LBM_WALLPSI_SELF = 16,
     LBM_VEL_LITERAL = 32,
-    LBM_FORCE_DENSITY = 64
+    LBM_FORCE_DENSITY = 64,
+    LBM_ROUND_STOCHASTIC = 128
 };
+
+/* Tile schedule bits for lbm_set_tile. */
+enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2 };
 
 /* Contact-angle wall kinds for lbm_contact_angle. */
 enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
@@ -125,6 +135,14 @@ int lbm_get_populations_window(lbm_ctx *c, int x0, int y0, int w, int h, double 
  * parameters and initial fields. */
 int lbm_step(lbm_ctx *c, int n);
 
+/* Fused diagnostics: with every > 0, every step whose start time t is a
+ * multiple of `every` also accumulates the lbm_reduce() quantities of time
+ * t inside the step kernel (no extra pass over the populations); the
+ * latest record stays on the device until lbm_get_diag copies it (with its
+ * time in *t_diag).  every = 0 turns this off.  ESTATE if no record exists. */
+int lbm_set_diag_interval(lbm_ctx *c, int every);
+int lbm_get_diag(lbm_ctx *c, double out[8], long *t_diag);
+
 /* Wait for all work of the context; EDEVICE if a kernel failed. */
 int lbm_synchronize(lbm_ctx *c);
 
@@ -169,11 +187,18 @@ int lbm_get_tables(lbm_ctx *c, uint8_t *link, int32_t *nw_list, int32_t *nw_src,
 int lbm_set_stream(lbm_ctx *c, void *hip_stream);
 
 /* Tile shape of the step kernel: block in {64, 128, 256} threads (strip
- * width block - 4 columns) and target rows per workgroup segment (>= 1).
- * lbm_autotune times the candidates for `steps` steps each on the current
- * state (restoring it afterwards) and keeps the fastest. */
-int lbm_set_tile(lbm_ctx *c, int block, int seg_rows);
-int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows);
+ * width block - 4 columns) and rows per workgroup segment.  seg_rows = 0
+ * (the default) is persistent scheduling: one work unit per resident
+ * workgroup, each taking an equal share of the strip rows.  Results do not
+ * depend on the tile shape (bitwise).  sched bits: LBM_SCHED_ALIGN makes
+ * strips a multiple of 128 bytes wide from x = 0, so that stores never
+ * cover part of a cache line shared with another workgroup;
+ * LBM_SCHED_BANDS (fixed segments only) runs units across the strips
+ * first, so concurrent workgroups cover whole rows.  lbm_autotune times the candidates
+ * for `steps` steps each on the current state (restoring it afterwards)
+ * and keeps the fastest. */
+int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched);
+int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows, unsigned *sched);
 int lbm_autotune(lbm_ctx *c, int steps);
 
 /* Checkpoint: populations, time, parameters.  EIO on file errors; load

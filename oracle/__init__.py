@@ -71,6 +71,7 @@ def lib():
             "oracle_node_forces": (I, [P, I, I, P]),
             "oracle_adhesion_vector": (I, [P, I, I, P]),
             "oracle_circle_fit": (I, [P, P, I, P]),
+            "oracle_threads": (I, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -240,3 +241,7 @@ def circle_fit(px, py):
     if rc:
         raise OracleError(rc, "circle fit failed")
     return out
+
+
+def threads():
+    return lib().oracle_threads()

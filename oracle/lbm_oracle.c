@@ -23,6 +23,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ */
 /* Lattice constants                                                   */
@@ -813,4 +816,13 @@ int oracle_contact_angle(oracle_ctx *c, int kind, const double wall[3], double *
     if (cth < -1.0) cth = -1.0;
     *theta_deg = acos(cth) * 180.0 / M_PI;
     return ORC_OK;
+}
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -85,6 +85,9 @@ int oracle_interface_points(oracle_ctx *c, int wall_kind, const double wall[3],
 int oracle_get_tables(const oracle_ctx *c, uint8_t *link, int32_t *nw_list,
                       int32_t *nw_src, int *n_nw);
 
+/* OpenMP threads the row loops use (1 without OpenMP). */
+int oracle_threads(void);
+
 /* ---- pieces exposed for unit pins ---- */
 void oracle_d2q9(int ex[9], int ey[9], double w[9], int opp[9]);
 void oracle_e8(int ex[24], int ey[24], double W[24], int copy_from[24]);

@@ -36,7 +36,11 @@ struct lbm_ctx {
     double rho0[2] = {0, 0};
     bool have_geom = false, have_params = false, have_fields = false;
     long t = 0;
-    int block = 256, seg_rows = 64;
+    int block = 256, seg_rows = 0;
+    unsigned sched = 0;
+    int diag_every = 0;
+    int cus = 0;
+    long diag_t = -1;
     std::string err;
 };
 
@@ -100,8 +104,12 @@ KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int 
     p.nx = c->nx;
     p.ny = c->ny;
     p.flags = c->flags;
-    tile_counts(block, seg_rows, c->nx, c->ny, &p.n_strips, &p.n_segs);
+    tile_counts(block, seg_rows, c->nx, c->ny, &p.n_strips, &p.n_segs, c->sched,
+                (int)(128 / elem_size(c->storage)), &p.strip_w);
+    p.band_order = (c->sched & SCHED_BANDS) ? 1 : 0;
+    p.n_units = p.n_strips * p.n_segs;
     p.item0 = 0;
+    p.tick = (unsigned)c->t;
     p.N = c->N;
     fill_physics<C>(p, c->flags, c->Gc, c->Gw1, c->Gw2, c->delta, c->tau, c->acc, c->rho0, c->storage != LBM_F64);
     return p;
@@ -112,8 +120,7 @@ int grid_of(int strips, int segs) { return ((strips * segs + 7) / 8) * 8; }
 template <int S, int BLOCK, int MODE>
 hipError_t launch_step_t(const KParams<typename Traits<S>::C> &p, hipStream_t st)
 {
-    const int items = p.n_strips * p.n_segs;
-    const int per_xcd = (items + 7) / 8;
+    const int per_xcd = (p.n_units + 7) / 8;
     hipLaunchKernelGGL((k_step<S, BLOCK, MODE>), dim3(per_xcd * 8), dim3(BLOCK), 0, st, p, per_xcd);
     return hipGetLastError();
 }
@@ -128,6 +135,29 @@ hipError_t launch_step_b(const KParams<typename Traits<S>::C> &p, int block, hip
     }
 }
 
+template <int S, int BLOCK>
+int occupancy_of()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_step<S, BLOCK, M_STORE>, BLOCK, 0) !=
+        hipSuccess)
+        nb = 1;
+    return std::max(nb, 1);
+}
+
+// Workgroups of the step kernel that fit on the device at once.
+template <int S>
+int resident_capacity(lbm_ctx *c, int block)
+{
+    if (c->cus <= 0) {
+        hipDeviceProp_t prop;
+        c->cus = (hipGetDeviceProperties(&prop, c->device) == hipSuccess) ? prop.multiProcessorCount : 256;
+    }
+    const int per_cu = block == 64 ? occupancy_of<S, 64>() : block == 128 ? occupancy_of<S, 128>()
+                                                                           : occupancy_of<S, 256>();
+    return per_cu * c->cus;
+}
+
 // Kinds of pass over the lattice.
 enum Pass { P_STEP, P_STEP_REDUCE, P_FIELDS_REDUCE, P_TABLES };
 
@@ -138,8 +168,15 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
 {
     using C = typename Traits<S>::C;
     const int block = (pass == P_STEP || pass == P_STEP_REDUCE) ? c->block : 256;
-    KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, c->seg_rows);
-    const int grid = grid_of(p.n_strips, p.n_segs);
+    const int seg = c->seg_rows > 0 ? c->seg_rows : 64;
+    KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, seg);
+    if (c->seg_rows == 0 && (pass == P_STEP || pass == P_STEP_REDUCE)) {
+        // persistent: one unit per resident workgroup, balanced rows per unit
+        const int cap = resident_capacity<S>(c, block);
+        const long long rows = (long long)p.n_strips * c->ny;
+        p.n_units = (int)std::max(1LL, std::min((long long)cap, rows));
+    }
+    const int grid = ((p.n_units + 7) / 8) * 8;
     if (nparts) *nparts = grid;
     if (pass == P_STEP_REDUCE || pass == P_FIELDS_REDUCE) {
         int rc = ensure_partials(c, (size_t)grid);
@@ -196,27 +233,6 @@ int inverse_stream(lbm_ctx *c, const double *fsrc, const double *rho)
     case LBM_F32: return inverse_stream_t<ST_F32>(c, fsrc, rho);
     case LBM_F16: return inverse_stream_t<ST_F16>(c, fsrc, rho);
     default: return inverse_stream_t<ST_BF16>(c, fsrc, rho);
-    }
-}
-
-template <int S>
-int pull_populations_t(lbm_ctx *c, double *out)
-{
-    using C = typename Traits<S>::C;
-    KParams<C> p = make_params<C>(c, c->buf[c->cur], nullptr, 256, 64);
-    const long long blocks = (c->N + 255) / 256;
-    hipLaunchKernelGGL((k_pull_populations<S>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, out);
-    HIPCHK(c, hipGetLastError());
-    return LBM_OK;
-}
-
-int pull_populations(lbm_ctx *c, double *out)
-{
-    switch (c->storage) {
-    case LBM_F64: return pull_populations_t<ST_F64>(c, out);
-    case LBM_F32: return pull_populations_t<ST_F32>(c, out);
-    case LBM_F16: return pull_populations_t<ST_F16>(c, out);
-    default: return pull_populations_t<ST_BF16>(c, out);
     }
 }
 
@@ -284,7 +300,9 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
     *out = nullptr;
     if (nx < 5 || ny < 5 || (long long)nx * ny > (1LL << 30)) return LBM_EINVAL;
     if (storage < LBM_F64 || storage > LBM_BF16) return LBM_EINVAL;
-    if (flags & ~127u) return LBM_EINVAL;
+    if (flags & ~(unsigned)FL_ALL) return LBM_EINVAL;
+    // one component's 9 direction arrays are addressed through a 32-bit range
+    if ((long long)nx * ny * 9 * (long long)elem_size(storage) >= (1LL << 32)) return LBM_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LBM_EDEVICE;
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
@@ -310,7 +328,7 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
     }
     c->stream = c->own_stream;
     bool ok = hipMalloc(&c->buf[0], bytes) == hipSuccess && hipMalloc(&c->buf[1], bytes) == hipSuccess &&
-              hipMalloc(&c->d_solid, (size_t)c->N) == hipSuccess && hipMalloc(&c->d_out, 16 * sizeof(double)) == hipSuccess;
+              hipMalloc(&c->d_solid, (size_t)c->N) == hipSuccess && hipMalloc(&c->d_out, 32 * sizeof(double)) == hipSuccess;
     if (!ok) {
         lbm_destroy(c);
         return LBM_ENOMEM;
@@ -429,6 +447,7 @@ int lbm_init_fields(lbm_ctx *c, const double *rho1, const double *rho2)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_fields = true;
     c->t = 0;
+    c->diag_t = -1;
     return LBM_OK;
 }
 
@@ -469,7 +488,7 @@ int lbm_get_populations(lbm_ctx *c, double *f)
     if (!f) return set_err(c, LBM_EINVAL, "null output");
     rc = ensure_tmp(c, (size_t)c->N * 18 * sizeof(double));
     if (rc) return rc;
-    rc = pull_populations(c, c->d_tmp);
+    rc = pull_window(c, 0, 0, c->nx, c->ny, c->d_tmp);
     if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(f, c->d_tmp, (size_t)c->N * 18 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -501,11 +520,38 @@ int lbm_step(lbm_ctx *c, int n)
     if (rc) return rc;
     if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
     for (int s = 0; s < n; ++s) {
-        rc = run_pass(c, P_STEP, nullptr, nullptr, nullptr, nullptr, nullptr);
-        if (rc) return rc;
+        if (c->diag_every > 0 && c->t % c->diag_every == 0) {
+            int nparts = 0;
+            rc = run_pass(c, P_STEP_REDUCE, nullptr, nullptr, nullptr, nullptr, &nparts);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->d_partials, nparts, c->d_out + 16);
+            HIPCHK(c, hipGetLastError());
+            c->diag_t = c->t;
+        } else {
+            rc = run_pass(c, P_STEP, nullptr, nullptr, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+        }
         c->cur ^= 1;
         c->t += 1;
     }
+    return LBM_OK;
+}
+
+int lbm_set_diag_interval(lbm_ctx *c, int every)
+{
+    if (!c) return LBM_EINVAL;
+    if (every < 0) return set_err(c, LBM_EINVAL, "interval must be >= 0");
+    c->diag_every = every;
+    return LBM_OK;
+}
+
+int lbm_get_diag(lbm_ctx *c, double out[8], long *t_diag)
+{
+    if (!c || !out) return LBM_EINVAL;
+    if (c->diag_t < 0) return set_err(c, LBM_ESTATE, "no diagnostic record yet");
+    HIPCHK(c, hipMemcpyAsync(out, c->d_out + 16, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (t_diag) *t_diag = c->diag_t;
     return LBM_OK;
 }
 
@@ -624,20 +670,23 @@ int lbm_get_tables(lbm_ctx *c, uint8_t *link, int32_t *nw_list, int32_t *nw_src,
     return LBM_OK;
 }
 
-int lbm_set_tile(lbm_ctx *c, int block, int seg_rows)
+int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
 {
     if (!c) return LBM_EINVAL;
-    if (!valid_block(block) || seg_rows < 1) return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 1");
+    if (!valid_block(block) || seg_rows < 0 || (sched & ~3u))
+        return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..3");
     c->block = block;
     c->seg_rows = seg_rows;
+    c->sched = sched;
     return LBM_OK;
 }
 
-int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows)
+int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows, unsigned *sched)
 {
     if (!c) return LBM_EINVAL;
     if (block) *block = c->block;
     if (seg_rows) *seg_rows = c->seg_rows;
+    if (sched) *sched = c->sched;
     return LBM_OK;
 }
 
@@ -650,36 +699,41 @@ int lbm_autotune(lbm_ctx *c, int steps)
     void *backup = nullptr;
     if (hipMalloc(&backup, bytes) != hipSuccess) return set_err(c, LBM_ENOMEM, "autotune backup allocation failed");
     const int cur0 = c->cur;
-    const long t0 = c->t;
+    const long t0 = c->t, diag_t0 = c->diag_t;
     hipError_t e = hipMemcpyAsync(backup, c->buf[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     const int blocks[3] = {64, 128, 256};
-    const int rows[7] = {8, 16, 32, 64, 128, 256, 512};
+    const int rows[8] = {0, 8, 16, 32, 64, 128, 256, 512};
     int best_b = c->block, best_r = c->seg_rows;
+    unsigned best_s = c->sched;
     float best_ms = 1e30f;
-    for (int bi = 0; bi < 3 && e == hipSuccess && rc == LBM_OK; ++bi)
-        for (int ri = 0; ri < 7 && e == hipSuccess && rc == LBM_OK; ++ri) {
-            if (rows[ri] > c->ny && ri > 0) continue;
-            c->block = blocks[bi];
-            c->seg_rows = rows[ri];
-            rc = lbm_step(c, 1);  // warm-up
-            if (rc) break;
-            e = hipEventRecord(ev0, c->stream);
-            if (e != hipSuccess) break;
-            rc = lbm_step(c, steps);
-            if (rc) break;
-            e = hipEventRecord(ev1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(ev1);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-            if (e == hipSuccess && ms < best_ms) {
-                best_ms = ms;
-                best_b = blocks[bi];
-                best_r = rows[ri];
-            }
+    for (int cand = 0; cand < 3 * 8 * 4 && e == hipSuccess && rc == LBM_OK; ++cand) {
+        const int bi = cand / 32, ri = (cand / 4) % 8;
+        const unsigned sc = (unsigned)(cand % 4);
+        if (rows[ri] > c->ny && ri > 1) continue;
+        if (rows[ri] == 0 && (sc & SCHED_BANDS)) continue;  // bands need fixed segments
+        c->block = blocks[bi];
+        c->seg_rows = rows[ri];
+        c->sched = sc;
+        rc = lbm_step(c, 1);  // warm-up
+        if (rc) break;
+        e = hipEventRecord(ev0, c->stream);
+        if (e != hipSuccess) break;
+        rc = lbm_step(c, steps);
+        if (rc) break;
+        e = hipEventRecord(ev1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (e == hipSuccess && ms < best_ms) {
+            best_ms = ms;
+            best_b = blocks[bi];
+            best_r = rows[ri];
+            best_s = sc;
         }
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(c->buf[cur0], backup, bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -687,8 +741,10 @@ int lbm_autotune(lbm_ctx *c, int steps)
     (void)hipFree(backup);
     c->cur = cur0;
     c->t = t0;
+    c->diag_t = diag_t0;
     c->block = best_b;
     c->seg_rows = best_r;
+    c->sched = best_s;
     if (rc) return rc;
     if (e != hipSuccess) return set_err(c, LBM_EDEVICE, "autotune failed: %s", hipGetErrorString(e));
     return LBM_OK;

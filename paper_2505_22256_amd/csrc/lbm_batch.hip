@@ -49,6 +49,7 @@ struct lbm_batch {
     long long *d_offs = nullptr;
     WallDesc *d_walls = nullptr;
     double *d_out = nullptr;
+    unsigned *d_tick = nullptr;  // step counter read by the batched kernel
     hipStream_t stream = nullptr, own_stream = nullptr;
     bool use_graph = false;
     int graph_steps = 0;
@@ -103,6 +104,7 @@ KParams<C> run_params(const lbm_batch *b, const BatchRun &r, int storage, int bl
     p.ny = r.ny;
     p.flags = r.flags;
     tile_counts(block, seg_rows, r.nx, r.ny, &p.n_strips, &p.n_segs);
+    p.n_units = p.n_strips * p.n_segs;
     p.item0 = r.item0;
     p.N = (long long)r.nx * r.ny;
     fill_physics<C>(p, r.flags, r.Gc, r.Gw1, r.Gw2, 0.8, r.tau, r.acc, r.rho0, storage != LBM_F64);
@@ -149,7 +151,11 @@ hipError_t launch_batch_t(lbm_batch *b, int flip)
     using C = typename Traits<S>::C;
     const int per_xcd = (b->n_items + 7) / 8;
     hipLaunchKernelGGL((k_step_batch<S, BLOCK, M_STORE>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream,
-                       (const KParams<C> *)b->d_params, b->nruns, b->n_items, per_xcd, flip);
+                       (const KParams<C> *)b->d_params, b->nruns, b->n_items, per_xcd, flip,
+                       (const unsigned *)b->d_tick);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, b->stream, b->d_tick);
     return hipGetLastError();
 }
 
@@ -208,7 +214,7 @@ int fields_run_t(lbm_batch *b, int r)
     p.out_rho2 = b->d_fields + T + br.off;
     p.out_ux = b->d_fields + 2 * T + br.off;
     p.out_uy = b->d_fields + 3 * T + br.off;
-    const int grid = ((p.n_strips * p.n_segs + 7) / 8) * 8;
+    const int grid = ((p.n_units + 7) / 8) * 8;
     if (b->partials_cap < (size_t)grid) {
         if (b->d_partials) (void)hipFree(b->d_partials);
         b->d_partials = nullptr;
@@ -268,7 +274,7 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
     for (int r = 0; r < nruns; ++r) {
         const lbm_run_desc &d = runs[r];
         BatchRun &br = b->runs[(size_t)r];
-        if (d.nx < 5 || d.ny < 5 || !d.solid || !d.rho1 || !d.rho2 || (d.flags & ~127u) || !(d.tau > 0.5) ||
+        if (d.nx < 5 || d.ny < 5 || !d.solid || !d.rho1 || !d.rho2 || (d.flags & ~(unsigned)FL_ALL) || !(d.tau > 0.5) ||
             !std::isfinite(d.tau) || !std::isfinite(d.G_c) || !std::isfinite(d.G_ads) ||
             (d.wall_kind != LBM_WALL_FLAT && d.wall_kind != LBM_WALL_CYLINDER)) {
             delete b;
@@ -318,7 +324,8 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
          hipMalloc(&b->d_dims, (size_t)nruns * 2 * sizeof(int)) == hipSuccess &&
          hipMalloc(&b->d_offs, (size_t)nruns * sizeof(long long)) == hipSuccess &&
          hipMalloc(&b->d_walls, (size_t)nruns * sizeof(WallDesc)) == hipSuccess &&
-         hipMalloc(&b->d_out, (size_t)nruns * 6 * sizeof(double)) == hipSuccess;
+         hipMalloc(&b->d_out, (size_t)nruns * 6 * sizeof(double)) == hipSuccess &&
+         hipMalloc(&b->d_tick, sizeof(unsigned)) == hipSuccess;
     if (!ok) {
         lbm_batch_destroy(b);
         return LBM_ENOMEM;
@@ -341,6 +348,7 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
     if (e == hipSuccess) e = hipMemcpy(b->d_dims, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_offs, offs.data(), offs.size() * sizeof(long long), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_walls, walls.data(), walls.size() * sizeof(WallDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_tick, 0, sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(b->buf[0], 0xff, bytes);
     if (e == hipSuccess) e = hipMemset(b->buf[1], 0xff, bytes);
     if (e != hipSuccess) {
@@ -374,7 +382,7 @@ void lbm_batch_destroy(lbm_batch *b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graphs(b);
     void *ptrs[] = {b->buf[0], b->buf[1], b->d_params, b->d_solid, b->d_fields, b->d_partials,
-                    b->d_dims, b->d_offs, b->d_walls, b->d_out};
+                    b->d_dims, b->d_offs, b->d_walls, b->d_out, b->d_tick};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
@@ -398,7 +406,7 @@ int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows)
 {
     if (!b) return LBM_EINVAL;
     if (!(block == 64 || block == 128 || block == 256) || seg_rows < 1)
-        return berr(b, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 1");
+        return berr(b, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 1 (batches use fixed segments)");
     b->block = block;
     b->seg_rows = seg_rows;
     return upload_params(b);

@@ -24,7 +24,9 @@ enum : unsigned {
     FL_COPY_OFF = 8u,
     FL_WALLPSI_SELF = 16u,
     FL_VEL_LITERAL = 32u,
-    FL_FORCE_DENSITY = 64u
+    FL_FORCE_DENSITY = 64u,
+    FL_ROUND_STOCHASTIC = 128u,
+    FL_ALL = 255u
 };
 
 // Kernel modes (bit set).
@@ -81,13 +83,17 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 
 template <int S> struct Traits;
 
+// dec/enc convert between the stored element and the compute type; the
+// stored value is the deviation g = f - w_i rho0_k (rho0 = 0 for FP64), and
+// the step works on deviations directly.
 template <> struct Traits<ST_F64> {
     using raw_t = double;
     using C = double;
     static constexpr bool deviation = false;
     __device__ static bool sent(raw_t v) { return __double_as_longlong(v) == -1LL; }
-    __device__ static C dec(raw_t v, C) { return v; }
-    __device__ static raw_t enc(C f, C) { return f; }
+    __device__ static C dec(raw_t v) { return v; }
+    __device__ static raw_t enc(C g) { return g; }
+    __device__ static raw_t enc_sr(C g, uint32_t) { return g; }
     __device__ static raw_t sentinel() { return __longlong_as_double(-1LL); }
 };
 template <> struct Traits<ST_F32> {
@@ -95,8 +101,9 @@ template <> struct Traits<ST_F32> {
     using C = float;
     static constexpr bool deviation = true;
     __device__ static bool sent(raw_t v) { return __float_as_uint(v) == 0xffffffffu; }
-    __device__ static C dec(raw_t v, C b) { return v + b; }
-    __device__ static raw_t enc(C f, C b) { return f - b; }
+    __device__ static C dec(raw_t v) { return v; }
+    __device__ static raw_t enc(C g) { return g; }
+    __device__ static raw_t enc_sr(C g, uint32_t) { return g; }
     __device__ static raw_t sentinel() { return __uint_as_float(0xffffffffu); }
 };
 template <> struct Traits<ST_F16> {
@@ -104,8 +111,16 @@ template <> struct Traits<ST_F16> {
     using C = float;
     static constexpr bool deviation = true;
     __device__ static bool sent(raw_t v) { return v == 0xffffu; }
-    __device__ static C dec(raw_t v, C b) { return (float)__builtin_bit_cast(_Float16, v) + b; }
-    __device__ static raw_t enc(C f, C b) { return __builtin_bit_cast(uint16_t, (_Float16)(f - b)); }
+    __device__ static C dec(raw_t v) { return (float)__builtin_bit_cast(_Float16, v); }
+    __device__ static raw_t enc(C g) { return __builtin_bit_cast(uint16_t, (_Float16)g); }
+    // Stochastic rounding: add 13 random bits below the FP16 mantissa of the
+    // FP32 value and truncate them; the result is exactly representable for
+    // normal FP16 values, so the conversion no longer rounds.
+    __device__ static raw_t enc_sr(C g, uint32_t r)
+    {
+        const uint32_t u = (__float_as_uint(g) + (r & 0x1fffu)) & ~0x1fffu;
+        return __builtin_bit_cast(uint16_t, (_Float16)__uint_as_float(u));
+    }
     __device__ static raw_t sentinel() { return 0xffffu; }
 };
 template <> struct Traits<ST_BF16> {
@@ -113,10 +128,76 @@ template <> struct Traits<ST_BF16> {
     using C = float;
     static constexpr bool deviation = true;
     __device__ static bool sent(raw_t v) { return v == 0xffffu; }
-    __device__ static C dec(raw_t v, C b) { return __uint_as_float((uint32_t)v << 16) + b; }
-    __device__ static raw_t enc(C f, C b) { return f32_to_bf16_rne(f - b); }
+    __device__ static C dec(raw_t v) { return __uint_as_float((uint32_t)v << 16); }
+    __device__ static raw_t enc(C g) { return f32_to_bf16_rne(g); }
+    // Stochastic rounding: add 16 random bits below the BF16 mantissa, truncate.
+    __device__ static raw_t enc_sr(C g, uint32_t r)
+    {
+        const uint32_t u = __float_as_uint(g);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
+        return (uint16_t)((u + (r & 0xffffu)) >> 16);
+    }
     __device__ static raw_t sentinel() { return 0xffffu; }
 };
+
+// ---------------------------------------------------------------------------
+// Population memory through buffer resources: one resource per component
+// (its 9 direction arrays, at most 4 GiB), the direction selected by a
+// scalar offset, the node by a 32-bit vector offset.  Accesses beyond the
+// resource return 0 / are dropped instead of faulting.
+// ---------------------------------------------------------------------------
+static constexpr int BUF_RSRC_WORD3 = 0x00020000;
+
+template <int S> struct PopMem {
+    __amdgpu_buffer_rsrc_t r[2];
+    uint32_t dstride;  // bytes between direction arrays
+};
+
+template <int S>
+__device__ __forceinline__ PopMem<S> make_mem(const void *base, long long N)
+{
+    using R = typename Traits<S>::raw_t;
+    PopMem<S> m;
+    const uint32_t ds = (uint32_t)(N * (long long)sizeof(R));
+    for (int k = 0; k < 2; ++k)
+        m.r[k] = __builtin_amdgcn_make_buffer_rsrc((char *)base + (long long)k * 9 * N * (long long)sizeof(R),
+                                                   (short)0, (int)(9u * ds), BUF_RSRC_WORD3);
+    m.dstride = ds;
+    return m;
+}
+
+// Vector offset that lies outside every resource (the load returns 0).
+static constexpr uint32_t OOB = 0xffffffffu;
+
+template <int S>
+__device__ __forceinline__ typename Traits<S>::raw_t pop_load(const PopMem<S> &m, int k, int i, uint32_t voff)
+{
+    using R = typename Traits<S>::raw_t;
+    if constexpr (sizeof(R) == 8) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(m.r[k], voff, (int)((uint32_t)i * m.dstride), 0);
+        return __builtin_bit_cast(R, v);
+    } else if constexpr (sizeof(R) == 4) {
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(m.r[k], voff, (int)((uint32_t)i * m.dstride), 0));
+    } else {
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b16(m.r[k], voff, (int)((uint32_t)i * m.dstride), 0));
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void pop_store(const PopMem<S> &m, int k, int i, uint32_t voff, typename Traits<S>::raw_t v)
+{
+    using R = typename Traits<S>::raw_t;
+    if constexpr (sizeof(R) == 8) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v),
+                                              m.r[k], voff, (int)((uint32_t)i * m.dstride), 0);
+    } else if constexpr (sizeof(R) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), m.r[k], voff,
+                                              (int)((uint32_t)i * m.dstride), 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), m.r[k], voff,
+                                              (int)((uint32_t)i * m.dstride), 0);
+    }
+}
 
 // Sentinel psi in the LDS tile (same all-ones pattern in the compute type).
 __device__ __forceinline__ bool lds_sent(float v) { return __float_as_uint(v) == 0xffffffffu; }
@@ -138,17 +219,43 @@ template <class C> struct KParams {
     int nx, ny;
     unsigned flags;
     int n_strips, n_segs;
+    int n_units;    // work units of the run (strips * segs, or the resident workgroup count)
+    int strip_w;    // > 0: strips of this width from x = 0 (the last one ragged); 0: balanced
+    int band_order; // 1: units run across strips first (row bands), 0: down each strip
     int item0;      // first work item of this run in a batch work list
+    unsigned tick;  // time step index (stochastic-rounding counter)
     long long N;    // nodes = array stride
     C omega, cforce, half, negGc, Gw1, Gw2, s1, s2, s3, t2, t3, delta;
     C g[2][2];
-    C base[2][9];   // w_i rho0_k (zero for FP64 storage)
+    C rho0[2];      // deviation base density per component (zero for FP64)
     // mode outputs
     double *out_rho1, *out_rho2, *out_ux, *out_uy;
     double *partials;
     uint8_t *tab_link, *tab_nw;
     int32_t *tab_src;
 };
+
+// Counter-based random bits for stochastic rounding: a murmur3-style
+// finaliser of (node, step) seeds a 32-bit LCG that yields one word per
+// stored population.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint32_t sr_seed(int node, unsigned tick)
+{
+    return mix32((uint32_t)node ^ mix32(tick * 0x9e3779b9u + 0x632be5abu));
+}
+__device__ __forceinline__ uint32_t lcg_next(uint32_t &s)
+{
+    s = s * 1664525u + 1013904223u;
+    return s >> 16;
+}
 
 // Position along one axis with its two neighbours, after periodic wrapping;
 // ok* false when the position falls outside a non-periodic domain.
@@ -182,77 +289,6 @@ template <class C> struct RowState {
     C f[2][9];
     int info;  // bit 8: solid or outside; bits 0-7: bounced-back directions
 };
-
-// Pull the populations f_i(x, t) = f*_i(x - e_i, t-1) of one node, with
-// halfway bounce-back f_i(x, t) = f*_opp(i)(x, t-1) where the source is
-// unavailable (Eq. 1 streaming; bounce-back of Sec. 3.1-3.5).  Computes the
-// densities rho_k (Eq. 3) with the same summation order as the definition.
-template <int S>
-__device__ __forceinline__ void pull_node(const KParams<typename Traits<S>::C> &p, int node,
-                                          const Axis &cx, const Axis &ry,
-                                          RowState<typename Traits<S>::C> &st,
-                                          typename Traits<S>::C &r1, typename Traits<S>::C &r2)
-{
-    using T = Traits<S>;
-    using C = typename T::C;
-    using R = typename T::raw_t;
-    const R *__restrict__ A = (const R *)p.A;
-    const long long N = p.N;
-    const int nx = p.nx;
-    R v[2][9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int ex = qx(i), ey = qy(i);
-        const int scol = ex == 1 ? cx.m : (ex == -1 ? cx.p : cx.c);
-        const bool okx = ex == 1 ? cx.okm : (ex == -1 ? cx.okp : true);
-        const int srow = ey == 1 ? ry.m : (ey == -1 ? ry.p : ry.c);
-        const bool oky = ey == 1 ? ry.okm : (ey == -1 ? ry.okp : true);
-        const bool ok = okx && oky;
-        const int src = ok ? srow * nx + scol : node;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            R val = A[(long long)(k * 9 + i) * N + src];
-            v[k][i] = ok ? val : T::sentinel();
-        }
-    }
-    st.info = 0;
-    if (T::sent(v[0][0])) {  // the node itself is solid
-        st.info = 256;
-        return;
-    }
-    C s1 = 0, s2 = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        st.f[0][i] = T::dec(v[0][i], p.base[0][i]);
-        st.f[1][i] = T::dec(v[1][i], p.base[1][i]);
-        s1 += st.f[0][i];
-        s2 += st.f[1][i];
-    }
-    if (__builtin_isnan(s1 + s2)) {
-        // some source is unavailable (or the state is non-finite): reflect
-        int info = 0;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            if (T::sent(v[0][i])) {
-                info |= 1 << (i - 1);
-#pragma unroll
-                for (int k = 0; k < 2; ++k) v[k][i] = A[(long long)(k * 9 + opp(i)) * N + node];
-            }
-        }
-        st.info = info;
-        s1 = 0;
-        s2 = 0;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            st.f[0][i] = T::dec(v[0][i], p.base[0][i]);
-            st.f[1][i] = T::dec(v[1][i], p.base[1][i]);
-            s1 += st.f[0][i];
-            s2 += st.f[1][i];
-        }
-    }
-    r1 = s1;
-    r2 = s2;
-}
 
 // Cohesion sums sum_n W_n e_n Psi_n over the 24 positions, by opposite
 // pairs (n, n+2) in each group of four (Eq. 8 on the E8 stencil).

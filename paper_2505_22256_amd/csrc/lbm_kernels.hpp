@@ -29,35 +29,212 @@ struct RedAcc {
     double m1 = 0, m2 = 0, px = 0, py = 0, umax = 0, rmin = __builtin_inf(), rmax = -__builtin_inf(), bad = 0;
 };
 
+// The 18 stored values pulled towards one node (prefetch unit).
+template <int S> struct RawRow {
+    typename Traits<S>::raw_t v[2][9];
+};
+
+// Source of direction i for a node at (cx, ry): the position x - e_i and
+// whether it lies inside the domain.
+__device__ __forceinline__ void pull_source(int i, const Axis &cx, const Axis &ry, int &col, int &row, bool &ok)
+{
+    const int ex = qx(i), ey = qy(i);
+    col = ex == 1 ? cx.m : (ex == -1 ? cx.p : cx.c);
+    row = ey == 1 ? ry.m : (ey == -1 ? ry.p : ry.c);
+    ok = (ex == 1 ? cx.okm : (ex == -1 ? cx.okp : true)) && (ey == 1 ? ry.okm : (ey == -1 ? ry.okp : true));
+}
+
+// Issue the loads of f*_i(x - e_i, t-1) for every direction (pull
+// streaming, Eq. 1).  Sources outside the domain and nodes that are not
+// valid get an out-of-range offset (the load returns 0 without traffic);
+// process_node substitutes the sentinel for them.
+template <int S>
+__device__ __forceinline__ void issue_node(const PopMem<S> &m, int nx, const Axis &cx, const Axis &ry, bool valid,
+                                           RawRow<S> &q)
+{
+    using R = typename Traits<S>::raw_t;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int col, row;
+        bool ok;
+        pull_source(i, cx, ry, col, row, ok);
+        const uint32_t voff = (valid && ok) ? (uint32_t)(row * nx + col) * (uint32_t)sizeof(R) : OOB;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) q.v[k][i] = pop_load<S>(m, k, i, voff);
+    }
+}
+
+// Turn the pulled values of one node into its state: deviations g_i of
+// f_i(x, t), with halfway bounce-back f_i(x, t) = f*_opp(i)(x, t-1) where
+// the source is unavailable (a sentinel or outside the domain), and the
+// densities rho_k = sum_i f_i (Eq. 3) in the definition's summation order.
+template <int S>
+__device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
+                                             const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
+                                             RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
+                                             typename Traits<S>::C &r2)
+{
+    using T = Traits<S>;
+    using C = typename T::C;
+    using R = typename T::raw_t;
+    st.info = 256;
+    if (!valid) return;
+    // the node's own rest slot is always inside the domain
+    if (T::sent(q.v[0][0])) return;  // solid node
+    C s1 = 0, s2 = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int col, row;
+        bool ok;
+        pull_source(i, cx, ry, col, row, ok);
+        // a source outside a non-periodic domain reads as the sentinel
+        st.f[0][i] = ok ? T::dec(q.v[0][i]) : T::dec(T::sentinel());
+        st.f[1][i] = ok ? T::dec(q.v[1][i]) : T::dec(T::sentinel());
+        s1 += st.f[0][i];
+        s2 += st.f[1][i];
+    }
+    s1 += p.rho0[0];
+    s2 += p.rho0[1];
+    st.info = 0;
+    if (__builtin_isnan(s1 + s2)) {
+        // an unavailable source (or a non-finite state): reflect
+        const uint32_t node = (uint32_t)(ry.c * p.nx + cx.c);
+        int info = 0;
+        s1 = 0;
+        s2 = 0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int col, row;
+            bool ok;
+            pull_source(i, cx, ry, col, row, ok);
+            if (i > 0 && (!ok || T::sent(q.v[0][i]))) {
+                info |= 1 << (i - 1);
+                st.f[0][i] = T::dec(pop_load<S>(m, 0, opp(i), node * (uint32_t)sizeof(R)));
+                st.f[1][i] = T::dec(pop_load<S>(m, 1, opp(i), node * (uint32_t)sizeof(R)));
+            }
+            s1 += st.f[0][i];
+            s2 += st.f[1][i];
+        }
+        st.info = info;
+        s1 += p.rho0[0];
+        s2 += p.rho0[1];
+    }
+    r1 = s1;
+    r2 = s2;
+}
+
+// Process a prefetched row: node state into `st`, psi into the LDS ring.
 template <int S, int BLOCK>
-__device__ __forceinline__ void pull_row(const KParams<typename Traits<S>::C> &p, const Axis &cx,
-                                         bool col_ok, int r,
-                                         PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
-                                         RowState<typename Traits<S>::C> &st)
+__device__ __forceinline__ void process_row(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
+                                            const Axis &cx, bool col_ok, int r, const RawRow<S> &q,
+                                            PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
+                                            RowState<typename Traits<S>::C> &st)
 {
     using C = typename Traits<S>::C;
     const Axis ry = make_axis(r, p.ny, p.flags & FL_PERIODIC_Y);
+    C r1 = 0, r2 = 0;
+    process_node<S>(p, m, cx, ry, col_ok && ry.ok, q, st, r1, r2);
     PsiPair<C> ps;
-    ps.a = lds_sentinel<C>();
-    ps.b = lds_sentinel<C>();
-    st.info = 256;
-    if (col_ok && ry.ok) {
-        const int node = ry.c * p.nx + cx.c;
-        C r1, r2;
-        pull_node<S>(p, node, cx, ry, st, r1, r2);
-        if (!(st.info & 256)) {
-            ps.a = r1;
-            ps.b = r2;
-        }
-    }
+    ps.a = (st.info & 256) ? lds_sentinel<C>() : r1;
+    ps.b = (st.info & 256) ? lds_sentinel<C>() : r2;
     ring[ring_slot(r)][threadIdx.x] = ps;
 }
 
-// Finish fluid-or-solid node (x, y) of an interior column: stencil, forces,
-// velocity, collision and the selected outputs.
+template <int S>
+__device__ __forceinline__ void issue_row(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
+                                          const Axis &cx, bool col_ok, int r, RawRow<S> &q)
+{
+    const Axis ry = make_axis(r, p.ny, p.flags & FL_PERIODIC_Y);
+    issue_node<S>(m, p.nx, cx, ry, col_ok && ry.ok, q);
+}
+
+// Bulk cohesion sums straight from the LDS ring, pair by pair (the same
+// order and operations as cohesion_sums on a gathered stencil).
+template <class C, int BLOCK>
+__device__ __forceinline__ void cohesion_sums_lds(PsiPair<C> (*ring)[BLOCK], int y, int tid, C &s1x, C &s1y, C &s2x,
+                                                  C &s2y)
+{
+    s1x = 0; s1y = 0; s2x = 0; s2y = 0;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int n = 4 * g + h, o = n + 2;
+            const PsiPair<C> a = ring[ring_slot(y + sy(n))][tid + sx(n)];
+            const PsiPair<C> b = ring[ring_slot(y + sy(o))][tid + sx(o)];
+            const C cx = (C)(e8wn(n) * sx(n));
+            const C cy = (C)(e8wn(n) * sy(n));
+            const C d1 = a.a - b.a;
+            const C d2 = a.b - b.b;
+            if (sx(n) != 0) { s1x += cx * d1; s2x += cx * d2; }
+            if (sy(n) != 0) { s1y += cy * d1; s2y += cy * d2; }
+        }
+    }
+}
+
+// Stencil value at position n after the wall rules of Sec. 2.4 / Table 1,
+// resolved on the fly from the ring (at most two LDS reads): an unavailable
+// first-layer position reads zero (or psi(x) under WALLPSI_SELF); an
+// unavailable second-layer position reads what its Table 1 partner
+// resolves to (zero under E8_COPY_OFF).  Same rules as apply_wall_rules.
+template <class C, int BLOCK>
+__device__ __forceinline__ PsiPair<C> resolve_position(PsiPair<C> (*vr)[BLOCK], int n, int y, int tid,
+                                                       C r1, C r2, unsigned flags, bool &unavailable)
+{
+    const PsiPair<C> v = vr[ring_slot(y + sy(n))][tid + sx(n)];
+    unavailable = lds_sent(v.a);
+    if (!unavailable) return v;
+    PsiPair<C> self, zero;
+    self.a = r1;
+    self.b = r2;
+    zero.a = 0;
+    zero.b = 0;
+    const PsiPair<C> first_rule = (flags & FL_WALLPSI_SELF) ? self : zero;
+    if (n < 8) return first_rule;
+    if (flags & FL_COPY_OFF) return zero;
+    const int m = table1(n);
+    const PsiPair<C> w = vr[ring_slot(y + sy(m))][tid + sx(m)];
+    return lds_sent(w.a) ? first_rule : w;
+}
+
+// Cohesion and adhesion sums at a node with unavailable stencil positions:
+// the same pair order as cohesion_sums / adhesion_vector, positions
+// resolved by the wall rules, S(x) from the unavailable positions.
+template <class C, int BLOCK>
+__device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int tid, C r1, C r2, unsigned flags,
+                                          C &s1x, C &s1y, C &s2x, C &s2y, C &Sx, C &Sy, uint32_t &unav)
+{
+    // read the stencil afresh rather than keeping the bulk path's values
+    // alive across the branch (a compiler-only memory clobber, no code)
+    asm volatile("" ::: "memory");
+    s1x = 0; s1y = 0; s2x = 0; s2y = 0;
+    Sx = 0; Sy = 0;
+    unav = 0;
+#pragma unroll
+    for (int g = 0; g < 6; ++g) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int n = 4 * g + h, o = n + 2;
+            bool un, uo;
+            const PsiPair<C> a = resolve_position<C, BLOCK>(vr, n, y, tid, r1, r2, flags, un);
+            const PsiPair<C> b = resolve_position<C, BLOCK>(vr, o, y, tid, r1, r2, flags, uo);
+            unav |= ((uint32_t)un << n) | ((uint32_t)uo << o);
+            const C cx = (C)(e8wn(n) * sx(n));
+            const C cy = (C)(e8wn(n) * sy(n));
+            const C d1 = a.a - b.a;
+            const C d2 = a.b - b.b;
+            const C ds = (C)(int)un - (C)(int)uo;
+            if (sx(n) != 0) { s1x += cx * d1; s2x += cx * d2; Sx += cx * ds; }
+            if (sy(n) != 0) { s1y += cy * d1; s2y += cy * d2; Sy += cy * ds; }
+        }
+    }
+}
+
+// Finish node (x, y) of an interior column: stencil, forces, velocity,
+// collision and the selected outputs.
 template <int S, int BLOCK, int MODE>
-__device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C> &p, const Axis &cx, int y,
-                                            const RowState<typename Traits<S>::C> &st,
+__device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mw,
+                                            const Axis &cx, int y, const RowState<typename Traits<S>::C> &st,
                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
 {
     using T = Traits<S>;
@@ -83,7 +260,8 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
     const PsiPair<C> ctr = ring[ring_slot(y)][tid];
     const C r1 = ctr.a, r2 = ctr.b;
 
-    // first moments j_k = sum_i f_i e_i (Eq. 4), definition order
+    // first moments j_k = sum_i f_i e_i (Eq. 4), definition order; the
+    // deviation base w_i rho0 has zero first moment
     const C(&f)[2][9] = st.f;
     C jx[2], jy[2];
 #pragma unroll
@@ -104,32 +282,21 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         jy[k] = ay;
     }
 
-    // E8 stencil of psi around x
-    PsiPair<C> P[24];
-#pragma unroll
-    for (int n = 0; n < 24; ++n) P[n] = ring[ring_slot(y + sy(n))][tid + sx(n)];
-
+    // E8 cohesion sums (Eq. 8); a sentinel (unavailable position) turns
+    // them into NaN and selects the wall path
     C s1x, s1y, s2x, s2y;
-    cohesion_sums<C>(P, s1x, s1y, s2x, s2y);
+    cohesion_sums_lds<C, BLOCK>(ring, y, tid, s1x, s1y, s2x, s2y);
     uint32_t unav = 0;
     C Sx = 0, Sy = 0;
     const bool near = __builtin_isnan(s1x + s1y + s2x + s2y);
-    if (near || (MODE & M_TABLES)) {
-#pragma unroll
-        for (int n = 0; n < 24; ++n) unav |= (uint32_t)lds_sent(P[n].a) << n;
-    }
     if (near) {
-        PsiPair<C> self, zero;
-        self.a = r1;
-        self.b = r2;
-        zero.a = 0;
-        zero.b = 0;
-        apply_wall_rules<PsiPair<C>>(P, unav, self, zero, p.flags);
-        cohesion_sums<C>(P, s1x, s1y, s2x, s2y);
-        adhesion_vector<C>(unav, Sx, Sy);
+        wall_sums<C, BLOCK>(ring, y, tid, r1, r2, p.flags, s1x, s1y, s2x, s2y, Sx, Sy, unav);
     }
 
     if (MODE & M_TABLES) {
+        unav = 0;
+#pragma unroll
+        for (int n = 0; n < 24; ++n) unav |= (uint32_t)lds_sent(ring[ring_slot(y + sy(n))][tid + sx(n)].a) << n;
         p.tab_link[node] = (uint8_t)(st.info & 255);
         p.tab_nw[node] = unav ? 1 : 0;
         if (unav) {
@@ -198,13 +365,15 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
     }
 
     if (MODE & M_STORE) {
-        // BGK with Guo forcing (Eq. 1, 2, 6, 7):
-        // f* = f + omega (f^eq - f) + (1 - omega/2) F_i,
-        // f^eq = w rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u],
+        // BGK with Guo forcing (Eq. 1, 2, 6, 7) on deviations g = f - w rho0:
+        // g* = g + omega (w (rho A_i - rho0) - g) + (1 - omega/2) F_i,
+        // A_i = 1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u   (f^eq = w rho A_i),
         // F_i = w [3 (e.F - u.F) + 9 (e.u)(e.F)].
-        R *__restrict__ B = (R *)p.B;
         const C a0 = (C)1 - (C)1.5 * (ux * ux + uy * uy);
         const C rho[2] = {r1, r2};
+        const bool sr = (S == ST_F16 || S == ST_BF16) && (p.flags & FL_ROUND_STOCHASTIC);
+        uint32_t rs = sr ? sr_seed(node, p.tick) : 0u;
+        const uint32_t voff = (uint32_t)node * (uint32_t)sizeof(R);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const C uF = ux * Fx[k] + uy * Fy[k];
@@ -214,10 +383,17 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
                 const int ex = qx(i), ey = qy(i);
                 const C eu = (C)ex * ux + (C)ey * uy;
                 const C eF = (C)ex * Fx[k] + (C)ey * Fy[k];
-                const C feq = w * rho[k] * (a0 + eu * ((C)3 + (C)4.5 * eu));
+                const C geq = w * (rho[k] * (a0 + eu * ((C)3 + (C)4.5 * eu)) - p.rho0[k]);
                 const C Fi = w * ((C)3 * (eF - uF) + (C)9 * eu * eF);
-                const C fs = f[k][i] + p.omega * (feq - f[k][i]) + p.cforce * Fi;
-                B[(long long)(k * 9 + i) * p.N + node] = T::enc(fs, p.base[k][i]);
+                const C gs = f[k][i] + p.omega * (geq - f[k][i]) + p.cforce * Fi;
+                R out;
+                if (S == ST_F16 || S == ST_BF16) {
+                    if (sr) out = T::enc_sr(gs, lcg_next(rs));
+                    else out = T::enc(gs);
+                } else {
+                    out = T::enc(gs);
+                }
+                pop_store<S>(mw, k, i, voff, out);
             }
         }
     }
@@ -256,17 +432,25 @@ __device__ void block_reduce_write(RedAcc acc, double *out)
         for (int q = 0; q < 8; ++q) out[q] = red[q][0];
 }
 
-// Process one (strip, segment) work item of a run.
+// March down rows [y0, y1) of one strip.  Each iteration processes the row
+// whose loads were issued one iteration earlier (psi into the ring), issues
+// the loads of the next row, synchronises once and finishes row y; the
+// populations of rows y, y+1 and y+2 stay in registers.
 template <int S, int BLOCK, int MODE>
-__device__ __forceinline__ void process_item(const KParams<typename Traits<S>::C> &p, int strip, int seg,
-                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
+__device__ __forceinline__ void process_segment(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mr,
+                                                const PopMem<S> &mw, int strip, int y0, int y1,
+                                                PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
 {
     using C = typename Traits<S>::C;
     const int tid = threadIdx.x;
-    const int x0 = (int)(((long long)strip * p.nx) / p.n_strips);
-    const int x1 = (int)(((long long)(strip + 1) * p.nx) / p.n_strips);
-    const int y0 = (int)(((long long)seg * p.ny) / p.n_segs);
-    const int y1 = (int)(((long long)(seg + 1) * p.ny) / p.n_segs);
+    int x0, x1;
+    if (p.strip_w > 0) {
+        x0 = strip * p.strip_w;
+        x1 = x0 + p.strip_w < p.nx ? x0 + p.strip_w : p.nx;
+    } else {
+        x0 = (int)(((long long)strip * p.nx) / p.n_strips);
+        x1 = (int)(((long long)(strip + 1) * p.nx) / p.n_strips);
+    }
     const int w = x1 - x0;
     const bool active = tid < w + 4;
     const bool interior = tid >= 2 && tid < w + 2;
@@ -274,78 +458,123 @@ __device__ __forceinline__ void process_item(const KParams<typename Traits<S>::C
     const bool col_ok = active && cx.ok;
 
     RowState<C> ra, rb, rc;
-    pull_row<S, BLOCK>(p, cx, col_ok, y0 - 2, ring, ra);
-    pull_row<S, BLOCK>(p, cx, col_ok, y0 - 1, ring, ra);
-    pull_row<S, BLOCK>(p, cx, col_ok, y0, ring, ra);
-    pull_row<S, BLOCK>(p, cx, col_ok, y0 + 1, ring, rb);
+    RawRow<S> q;
+    issue_row<S>(p, mr, cx, col_ok, y0 - 2, q);
+    process_row<S, BLOCK>(p, mr, cx, col_ok, y0 - 2, q, ring, ra);
+    issue_row<S>(p, mr, cx, col_ok, y0 - 1, q);
+    process_row<S, BLOCK>(p, mr, cx, col_ok, y0 - 1, q, ring, ra);
+    issue_row<S>(p, mr, cx, col_ok, y0, q);
+    process_row<S, BLOCK>(p, mr, cx, col_ok, y0, q, ring, ra);
+    issue_row<S>(p, mr, cx, col_ok, y0 + 1, q);
+    process_row<S, BLOCK>(p, mr, cx, col_ok, y0 + 1, q, ring, rb);
+    issue_row<S>(p, mr, cx, col_ok, y0 + 2, q);
     int y = y0;
     for (;;) {
         if (y >= y1) break;
-        pull_row<S, BLOCK>(p, cx, col_ok, y + 2, ring, rc);
+        process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rc);
+        issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
-        if (interior) finish_node<S, BLOCK, MODE>(p, cx, y, ra, ring, acc);
+        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, ra, ring, acc);
         ++y;
         if (y >= y1) break;
-        pull_row<S, BLOCK>(p, cx, col_ok, y + 2, ring, ra);
+        process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, ra);
+        issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
-        if (interior) finish_node<S, BLOCK, MODE>(p, cx, y, rb, ring, acc);
+        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, rb, ring, acc);
         ++y;
         if (y >= y1) break;
-        pull_row<S, BLOCK>(p, cx, col_ok, y + 2, ring, rb);
+        process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rb);
+        issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
-        if (interior) finish_node<S, BLOCK, MODE>(p, cx, y, rc, ring, acc);
+        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, rc, ring, acc);
         ++y;
     }
 }
 
+// Rows of a run are numbered strip-major (strip * ny + y).  Work unit u of
+// n_units covers rows [u * R / n_units, (u + 1) * R / n_units) of the R =
+// strips * ny rows, split where it crosses a strip boundary.  With
+// band_order the units of a fixed-segment tiling are taken across the
+// strips first, so that workgroups running at the same time cover whole
+// rows of the lattice.
+template <int S, int BLOCK, int MODE>
+__device__ __forceinline__ void process_unit(const KParams<typename Traits<S>::C> &p, int u, int n_units,
+                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
+{
+    const PopMem<S> mr = make_mem<S>(p.A, p.N);
+    const PopMem<S> mw = make_mem<S>(p.B, p.N);
+    if (p.band_order && n_units == p.n_strips * p.n_segs) {
+        const int strip = u % p.n_strips, seg = u / p.n_strips;
+        const int y0 = (int)(((long long)seg * p.ny) / p.n_segs);
+        const int y1 = (int)(((long long)(seg + 1) * p.ny) / p.n_segs);
+        process_segment<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring, acc);
+        return;
+    }
+    const long long R = (long long)p.n_strips * p.ny;
+    long long q0 = (long long)u * R / n_units;
+    const long long q1 = (long long)(u + 1) * R / n_units;
+    bool first = true;
+    while (q0 < q1) {
+        const int strip = (int)(q0 / p.ny);
+        const int y0 = (int)(q0 - (long long)strip * p.ny);
+        const long long end = (long long)(strip + 1) * p.ny < q1 ? (long long)(strip + 1) * p.ny : q1;
+        const int y1 = (int)(end - (long long)strip * p.ny);
+        if (!first) __syncthreads();  // the ring is reused
+        process_segment<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring, acc);
+        first = false;
+        q0 = end;
+    }
+}
+
 // One time step (or one field/diagnostic/table pass) of a single run.
-// Grid: 8 * per_xcd workgroups; workgroup b takes item (b % 8) * per_xcd + b / 8.
+// Grid: 8 * per_xcd workgroups over the run's n_units units;
+// workgroup b takes unit (b % 8) * per_xcd + b / 8, so each XCD works on a
+// contiguous part of the lattice.
 template <int S, int BLOCK, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_step(const KParams<typename Traits<S>::C> p, int per_xcd)
 {
     using C = typename Traits<S>::C;
     __shared__ PsiPair<C> ring[8][BLOCK];
     const int b = blockIdx.x;
-    const int item = (b & 7) * per_xcd + (b >> 3);
+    const int unit = (b & 7) * per_xcd + (b >> 3);
     RedAcc acc;
-    if (item < p.n_strips * p.n_segs) {
-        const int strip = item / p.n_segs;
-        process_item<S, BLOCK, MODE>(p, strip, item - strip * p.n_segs, ring, acc);
-    }
+    if (unit < p.n_units) process_unit<S, BLOCK, MODE>(p, unit, p.n_units, ring, acc);
     if (MODE & M_REDUCE) {
         __syncthreads();
         block_reduce_write<BLOCK>(acc, p.partials + (long long)b * 8);
     }
 }
 
-// Batched step: the work list concatenates the (strip, segment) items of
-// all runs; run r owns items [item0_r, item0_r + strips_r * segs_r).
+// Batched step: the work list concatenates the units of all runs; run r
+// owns units [item0_r, item0_r + strips_r * segs_r).
 template <int S, int BLOCK, int MODE>
 __global__ void __launch_bounds__(BLOCK)
-k_step_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns, int n_items, int per_xcd, int flip)
+k_step_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns, int n_items, int per_xcd, int flip,
+             const unsigned *__restrict__ tick)
 {
     using C = typename Traits<S>::C;
     __shared__ PsiPair<C> ring[8][BLOCK];
     const int b = blockIdx.x;
     const int item = (b & 7) * per_xcd + (b >> 3);
     if (item >= n_items) return;
-    // binary search for the run owning this item
     int lo = 0, hi = nruns - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (runs[mid].item0 <= item) lo = mid; else hi = mid - 1;
     }
     KParams<C> p = runs[lo];
+    p.tick = *tick;
     if (flip) {
         const void *t = p.A;
         p.A = p.B;
         p.B = (void *)t;
     }
-    const int local = item - p.item0;
-    const int strip = local / p.n_segs;
     RedAcc acc;
-    process_item<S, BLOCK, MODE>(p, strip, local - strip * p.n_segs, ring, acc);
+    process_unit<S, BLOCK, MODE>(p, item - p.item0, p.n_units, ring, acc);
 }
+
+// Advance the batch step counter (one thread; graph-capturable).
+static __global__ void k_tick(unsigned *tick) { tick[0] += 1u; }
 
 // Finalise diagnostics: deterministic compensated (Neumaier) sums over the
 // workgroup partials in a fixed order; one workgroup of 256 threads.
@@ -404,18 +633,19 @@ static __global__ void __launch_bounds__(256) k_reduce_final(const double *__res
 // slot (z, j) is pulled by z + e_j when that position is available, else by
 // z itself as the bounce-back of direction opp(j).  So
 // f*_j(z) = f_j(z + e_j) or f_opp(j)(z).  Source f is FP64 [2][9][N]; when
-// `rho` is given instead, f_i = w_i rho_k (equilibrium at rest).
+// `rho` is given instead, f_i = w_i rho_k (equilibrium at rest).  Stored as
+// the deviation f - w_j rho0_k.
 template <int S>
 __global__ void __launch_bounds__(256)
 k_inverse_stream(const KParams<typename Traits<S>::C> p, const uint8_t *__restrict__ solid,
                  const double *__restrict__ fsrc, const double *__restrict__ rho)
 {
     using T = Traits<S>;
-    using R = typename T::raw_t;
+    using C = typename T::C;
     const long long z = (long long)blockIdx.x * 256 + threadIdx.x;
     if (z >= p.N) return;
-    R *__restrict__ A = (R *)p.B;
     if (solid[z]) return;  // slots stay at the sentinel
+    const PopMem<S> m = make_mem<S>(p.B, p.N);
     const int x = (int)(z % p.nx), y = (int)(z / p.nx);
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
@@ -430,52 +660,41 @@ k_inverse_stream(const KParams<typename Traits<S>::C> p, const uint8_t *__restri
             } else {
                 v = avail ? fsrc[(long long)(k * 9 + j) * p.N + nb] : fsrc[(long long)(k * 9 + opp(j)) * p.N + z];
             }
-            A[(long long)(k * 9 + j) * p.N + z] = T::enc((typename T::C)v, p.base[k][j]);
+            const double base = T::deviation ? qw(j) * (double)p.rho0[k] : 0.0;
+            pop_store<S>(m, k, j, (uint32_t)z * (uint32_t)sizeof(typename T::raw_t), T::enc((C)(v - base)));
         }
     }
 }
 
-// Pre-collision populations f(x, t) as FP64 [2][9][N] (solid -> 0), by the
+// Pre-collision populations f(x, t) = g + w_i rho0 as FP64 (solid -> 0) of
+// the w x h window at (x0, y0) (periodic wrap), out [2][9][h][w], by the
 // same pull as the step kernel.
-template <int S>
-__global__ void __launch_bounds__(256) k_pull_populations(const KParams<typename Traits<S>::C> p, double *__restrict__ out)
-{
-    using C = typename Traits<S>::C;
-    const long long z = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (z >= p.N) return;
-    const int x = (int)(z % p.nx), y = (int)(z / p.nx);
-    const Axis cx = make_axis(x, p.nx, p.flags & FL_PERIODIC_X);
-    const Axis ry = make_axis(y, p.ny, p.flags & FL_PERIODIC_Y);
-    RowState<C> st;
-    C r1, r2;
-    pull_node<S>(p, (int)z, cx, ry, st, r1, r2);
-    const bool solid = st.info & 256;
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int i = 0; i < 9; ++i) out[(long long)(k * 9 + i) * p.N + z] = solid ? 0.0 : (double)st.f[k][i];
-}
-
-// Same, for the w x h window at (x0, y0) (periodic wrap), out [2][9][h][w].
 template <int S>
 __global__ void __launch_bounds__(256)
 k_pull_window(const KParams<typename Traits<S>::C> p, int x0, int y0, int w, int h, double *__restrict__ out)
 {
-    using C = typename Traits<S>::C;
+    using T = Traits<S>;
+    using C = typename T::C;
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long M = (long long)w * h;
     if (q >= M) return;
     const int wx = (int)(q % w), wy = (int)(q / w);
     const Axis cx = make_axis(x0 + wx, p.nx, p.flags & FL_PERIODIC_X);
     const Axis ry = make_axis(y0 + wy, p.ny, p.flags & FL_PERIODIC_Y);
+    const PopMem<S> m = make_mem<S>(p.A, p.N);
+    RawRow<S> raw;
+    issue_node<S>(m, p.nx, cx, ry, true, raw);
     RowState<C> st;
     C r1, r2;
-    pull_node<S>(p, ry.c * p.nx + cx.c, cx, ry, st, r1, r2);
+    process_node<S>(p, m, cx, ry, true, raw, st, r1, r2);
     const bool solid = st.info & 256;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out[(long long)(k * 9 + i) * M + q] = solid ? 0.0 : (double)st.f[k][i];
+        for (int i = 0; i < 9; ++i) {
+            const double base = T::deviation ? qw(i) * (double)p.rho0[k] : 0.0;
+            out[(long long)(k * 9 + i) * M + q] = solid ? 0.0 : (double)st.f[k][i] + base;
+        }
 }
 
 // ---------------------------------------------------------------------------

@@ -11,9 +11,20 @@ namespace lbm_host {
 using lbm::KParams;
 using lbm::qw;
 
-inline void tile_counts(int block, int seg_rows, int nx, int ny, int *strips, int *segs)
+// Schedule bits of a tile (lbm_set_tile).
+enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u };
+
+// Strips are block - 4 columns wide (balanced over nx), or, with
+// SCHED_ALIGN, the widest multiple of `align_cols` columns that fits, from
+// x = 0, so that every strip's stores start on a 128-byte boundary.
+inline void tile_counts(int block, int seg_rows, int nx, int ny, int *strips, int *segs, unsigned sched = 0,
+                        int align_cols = 32, int *strip_w = nullptr)
 {
-    *strips = (nx + (block - 4) - 1) / (block - 4);
+    int w = block - 4;
+    if ((sched & SCHED_ALIGN) && w >= align_cols) w = (w / align_cols) * align_cols;
+    else if (sched & SCHED_ALIGN) w = block - 4;
+    *strips = (nx + w - 1) / w;
+    if (strip_w) *strip_w = (sched & SCHED_ALIGN) ? w : 0;
     const int s = (ny + seg_rows - 1) / seg_rows;
     *segs = std::max(1, std::min(s, ny));
 }
@@ -45,8 +56,7 @@ inline void fill_physics(KParams<C> &p, unsigned flags, double Gc, double Gw1, d
     p.t3 = (C)t3;
     for (int k = 0; k < 2; ++k)
         for (int a = 0; a < 2; ++a) p.g[k][a] = (C)acc[k][a];
-    for (int k = 0; k < 2; ++k)
-        for (int i = 0; i < 9; ++i) p.base[k][i] = deviation ? (C)(qw(i) * rho0[k]) : (C)0;
+    for (int k = 0; k < 2; ++k) p.rho0[k] = deviation ? (C)rho0[k] : (C)0;
 }
 
 }  // namespace lbm_host

@@ -22,7 +22,9 @@ OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EUNSTABLE, EIO = 0, -1, -2, -3, -4, -5, -6
 F64, F32, F16, BF16 = 0, 1, 2, 3
 PERIODIC_X, PERIODIC_Y = 1, 2
 SCHEME_ORIGINAL, E8_COPY_OFF, WALLPSI_SELF, VEL_LITERAL, FORCE_DENSITY = 4, 8, 16, 32, 64
+ROUND_STOCHASTIC = 128
 WALL_FLAT, WALL_CYLINDER = 0, 1
+SCHED_ALIGN, SCHED_BANDS = 1, 2
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 
 _P = ctypes.c_void_p
@@ -50,6 +52,8 @@ SIGNATURES = {
     "lbm_get_populations": (_I, [_P, _P]),
     "lbm_get_populations_window": (_I, [_P, _I, _I, _I, _I, _P]),
     "lbm_step": (_I, [_P, _I]),
+    "lbm_set_diag_interval": (_I, [_P, _I]),
+    "lbm_get_diag": (_I, [_P, _P, ctypes.POINTER(_L)]),
     "lbm_synchronize": (_I, [_P]),
     "lbm_time": (_L, [_P]),
     "lbm_get_fields": (_I, [_P, _P, _P, _P, _P]),
@@ -57,8 +61,8 @@ SIGNATURES = {
     "lbm_contact_angle": (_I, [_P, _I, _P, ctypes.POINTER(_D)]),
     "lbm_get_tables": (_I, [_P, _P, _P, _P, ctypes.POINTER(_I)]),
     "lbm_set_stream": (_I, [_P, _P]),
-    "lbm_set_tile": (_I, [_P, _I, _I]),
-    "lbm_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "lbm_set_tile": (_I, [_P, _I, _I, _U]),
+    "lbm_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_U)]),
     "lbm_autotune": (_I, [_P, _I]),
     "lbm_save": (_I, [_P, ctypes.c_char_p]),
     "lbm_load": (_I, [_P, ctypes.c_char_p]),
@@ -189,6 +193,15 @@ class Lattice:
     def step(self, n=1):
         self._c(self._L.lbm_step(self.h, int(n)))
 
+    def set_diag_interval(self, every):
+        self._c(self._L.lbm_set_diag_interval(self.h, int(every)))
+
+    def get_diag(self):
+        out = np.empty(8)
+        t = _L()
+        self._c(self._L.lbm_get_diag(self.h, _ptr(out), ctypes.byref(t)))
+        return out, t.value
+
     def synchronize(self):
         self._c(self._L.lbm_synchronize(self.h))
 
@@ -224,13 +237,13 @@ class Lattice:
     def set_stream(self, stream_handle: Optional[int]):
         self._c(self._L.lbm_set_stream(self.h, stream_handle))
 
-    def set_tile(self, block, seg_rows):
-        self._c(self._L.lbm_set_tile(self.h, block, seg_rows))
+    def set_tile(self, block, seg_rows, sched=0):
+        self._c(self._L.lbm_set_tile(self.h, block, seg_rows, sched))
 
     def get_tile(self):
-        b, r = _I(), _I()
-        self._c(self._L.lbm_get_tile(self.h, ctypes.byref(b), ctypes.byref(r)))
-        return b.value, r.value
+        b, r, s = _I(), _I(), _U()
+        self._c(self._L.lbm_get_tile(self.h, ctypes.byref(b), ctypes.byref(r), ctypes.byref(s)))
+        return b.value, r.value, s.value
 
     def autotune(self, steps=5):
         self._c(self._L.lbm_autotune(self.h, steps))
