@@ -86,7 +86,7 @@ enum {
 };
 
 /* Tile schedule bits for lbm_set_tile. */
-enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2 };
+enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2, LBM_SCHED_XCD_SLABS = 4 };
 
 /* Contact-angle wall kinds for lbm_contact_angle. */
 enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
@@ -194,7 +194,9 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * strips a multiple of 128 bytes wide from x = 0, so that stores never
  * cover part of a cache line shared with another workgroup;
  * LBM_SCHED_BANDS (fixed segments only) runs units across the strips
- * first, so concurrent workgroups cover whole rows.  lbm_autotune times the candidates
+ * first, so concurrent workgroups cover whole rows; LBM_SCHED_XCD_SLABS
+ * gives each of the 8 XCDs one contiguous slab of rows, one workgroup per
+ * strip marching down it (seg_rows is ignored).  lbm_autotune times the candidates
  * for `steps` steps each on the current state (restoring it afterwards)
  * and keeps the fastest. */
 int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched);

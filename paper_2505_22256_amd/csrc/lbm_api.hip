@@ -107,6 +107,7 @@ KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int 
     tile_counts(block, seg_rows, c->nx, c->ny, &p.n_strips, &p.n_segs, c->sched,
                 (int)(128 / elem_size(c->storage)), &p.strip_w);
     p.band_order = (c->sched & SCHED_BANDS) ? 1 : 0;
+    p.xcd_slabs = 0;
     p.n_units = p.n_strips * p.n_segs;
     p.item0 = 0;
     p.tick = (unsigned)c->t;
@@ -170,7 +171,14 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
     const int block = (pass == P_STEP || pass == P_STEP_REDUCE) ? c->block : 256;
     const int seg = c->seg_rows > 0 ? c->seg_rows : 64;
     KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, seg);
-    if (c->seg_rows == 0 && (pass == P_STEP || pass == P_STEP_REDUCE)) {
+    if ((c->sched & SCHED_XCD_SLABS) && (pass == P_STEP || pass == P_STEP_REDUCE)) {
+        // one unit per (strip, row slab); the grid is 8 * strips so that
+        // workgroup b lands on XCD b % 8 = its slab
+        p.xcd_slabs = 1;
+        p.band_order = 0;
+        p.n_segs = 8;
+        p.n_units = 8 * p.n_strips;
+    } else if (c->seg_rows == 0 && (pass == P_STEP || pass == P_STEP_REDUCE)) {
         // persistent: one unit per resident workgroup, balanced rows per unit
         const int cap = resident_capacity<S>(c, block);
         const long long rows = (long long)p.n_strips * c->ny;
@@ -334,6 +342,11 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
         return LBM_ENOMEM;
     }
     c->solid.assign((size_t)c->N, 0);
+    // measured defaults on the 16384 x 2048 channel: 16-row segments in row
+    // bands; 128-byte aligned strips pay off for 4- and 8-byte storage only
+    c->block = 256;
+    c->seg_rows = 16;
+    c->sched = (storage == LBM_F16 || storage == LBM_BF16) ? SCHED_BANDS : (SCHED_ALIGN | SCHED_BANDS);
     *out = c;
     return LBM_OK;
 }
@@ -673,8 +686,8 @@ int lbm_get_tables(lbm_ctx *c, uint8_t *link, int32_t *nw_list, int32_t *nw_src,
 int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
 {
     if (!c) return LBM_EINVAL;
-    if (!valid_block(block) || seg_rows < 0 || (sched & ~3u))
-        return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..3");
+    if (!valid_block(block) || seg_rows < 0 || (sched & ~7u))
+        return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..7");
     c->block = block;
     c->seg_rows = seg_rows;
     c->sched = sched;
@@ -709,11 +722,12 @@ int lbm_autotune(lbm_ctx *c, int steps)
     int best_b = c->block, best_r = c->seg_rows;
     unsigned best_s = c->sched;
     float best_ms = 1e30f;
-    for (int cand = 0; cand < 3 * 8 * 4 && e == hipSuccess && rc == LBM_OK; ++cand) {
-        const int bi = cand / 32, ri = (cand / 4) % 8;
-        const unsigned sc = (unsigned)(cand % 4);
+    for (int cand = 0; cand < 3 * 8 * 6 && e == hipSuccess && rc == LBM_OK; ++cand) {
+        const int bi = cand / 48, ri = (cand / 6) % 8;
+        const unsigned sc = (unsigned)(cand % 6);  // 0-3: align/bands bits; 4, 5: XCD slabs (+ align)
         if (rows[ri] > c->ny && ri > 1) continue;
         if (rows[ri] == 0 && (sc & SCHED_BANDS)) continue;  // bands need fixed segments
+        if ((sc & SCHED_XCD_SLABS) && ri != 0) continue;   // slabs ignore seg_rows
         c->block = blocks[bi];
         c->seg_rows = rows[ri];
         c->sched = sc;

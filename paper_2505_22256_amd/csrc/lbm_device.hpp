@@ -169,17 +169,25 @@ __device__ __forceinline__ PopMem<S> make_mem(const void *base, long long N)
 // Vector offset that lies outside every resource (the load returns 0).
 static constexpr uint32_t OOB = 0xffffffffu;
 
+// Cache-policy bits of the population loads and stores (bit 1: nt).
+#ifndef LBM_LOAD_AUX
+#define LBM_LOAD_AUX 0
+#endif
+#ifndef LBM_STORE_AUX
+#define LBM_STORE_AUX 0
+#endif
+
 template <int S>
 __device__ __forceinline__ typename Traits<S>::raw_t pop_load(const PopMem<S> &m, int k, int i, uint32_t voff)
 {
     using R = typename Traits<S>::raw_t;
     if constexpr (sizeof(R) == 8) {
-        auto v = __builtin_amdgcn_raw_buffer_load_b64(m.r[k], voff, (int)((uint32_t)i * m.dstride), 0);
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(m.r[k], voff, (int)((uint32_t)i * m.dstride), LBM_LOAD_AUX);
         return __builtin_bit_cast(R, v);
     } else if constexpr (sizeof(R) == 4) {
-        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(m.r[k], voff, (int)((uint32_t)i * m.dstride), 0));
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(m.r[k], voff, (int)((uint32_t)i * m.dstride), LBM_LOAD_AUX));
     } else {
-        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b16(m.r[k], voff, (int)((uint32_t)i * m.dstride), 0));
+        return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b16(m.r[k], voff, (int)((uint32_t)i * m.dstride), LBM_LOAD_AUX));
     }
 }
 
@@ -189,13 +197,13 @@ __device__ __forceinline__ void pop_store(const PopMem<S> &m, int k, int i, uint
     using R = typename Traits<S>::raw_t;
     if constexpr (sizeof(R) == 8) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v),
-                                              m.r[k], voff, (int)((uint32_t)i * m.dstride), 0);
+                                              m.r[k], voff, (int)((uint32_t)i * m.dstride), LBM_STORE_AUX);
     } else if constexpr (sizeof(R) == 4) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), m.r[k], voff,
-                                              (int)((uint32_t)i * m.dstride), 0);
+                                              (int)((uint32_t)i * m.dstride), LBM_STORE_AUX);
     } else {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), m.r[k], voff,
-                                              (int)((uint32_t)i * m.dstride), 0);
+                                              (int)((uint32_t)i * m.dstride), LBM_STORE_AUX);
     }
 }
 
@@ -222,10 +230,13 @@ template <class C> struct KParams {
     int n_units;    // work units of the run (strips * segs, or the resident workgroup count)
     int strip_w;    // > 0: strips of this width from x = 0 (the last one ragged); 0: balanced
     int band_order; // 1: units run across strips first (row bands), 0: down each strip
+    int xcd_slabs;  // 1: unit b = (strip b / 8, row slab b % 8): XCD j marches slab j
     int item0;      // first work item of this run in a batch work list
     unsigned tick;  // time step index (stochastic-rounding counter)
     long long N;    // nodes = array stride
     C omega, cforce, half, negGc, Gw1, Gw2, s1, s2, s3, t2, t3, delta;
+    C omw, cf3, cf9;     // 1 - omega, 3 (1 - omega/2), 9 (1 - omega/2)
+    C omega_rho0[2];     // omega * rho0_k
     C g[2][2];
     C rho0[2];      // deviation base density per component (zero for FP64)
     // mode outputs
@@ -263,6 +274,27 @@ struct Axis {
     int c, m, p;
     bool ok, okm, okp;
 };
+
+// Same as make_axis for a position at most one period outside [0, n).
+__device__ __forceinline__ Axis make_axis_near(int v, int n, bool periodic)
+{
+    Axis a;
+    if (periodic) {
+        const int w = v < 0 ? v + n : (v >= n ? v - n : v);
+        a.c = w;
+        a.m = (w == 0) ? n - 1 : w - 1;
+        a.p = (w == n - 1) ? 0 : w + 1;
+        a.ok = a.okm = a.okp = true;
+    } else {
+        a.c = v;
+        a.m = v - 1;
+        a.p = v + 1;
+        a.ok = v >= 0 && v < n;
+        a.okm = v - 1 >= 0 && v - 1 < n;
+        a.okp = v + 1 >= 0 && v + 1 < n;
+    }
+    return a;
+}
 
 __device__ __forceinline__ Axis make_axis(int v, int n, bool periodic)
 {

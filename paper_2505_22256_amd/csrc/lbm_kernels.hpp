@@ -131,7 +131,7 @@ __device__ __forceinline__ void process_row(const KParams<typename Traits<S>::C>
                                             RowState<typename Traits<S>::C> &st)
 {
     using C = typename Traits<S>::C;
-    const Axis ry = make_axis(r, p.ny, p.flags & FL_PERIODIC_Y);
+    const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
     C r1 = 0, r2 = 0;
     process_node<S>(p, m, cx, ry, col_ok && ry.ok, q, st, r1, r2);
     PsiPair<C> ps;
@@ -144,7 +144,7 @@ template <int S>
 __device__ __forceinline__ void issue_row(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
                                           const Axis &cx, bool col_ok, int r, RawRow<S> &q)
 {
-    const Axis ry = make_axis(r, p.ny, p.flags & FL_PERIODIC_Y);
+    const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
     issue_node<S>(m, p.nx, cx, ry, col_ok && ry.ok, q);
 }
 
@@ -366,26 +366,39 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
 
     if (MODE & M_STORE) {
         // BGK with Guo forcing (Eq. 1, 2, 6, 7) on deviations g = f - w rho0:
-        // g* = g + omega (w (rho A_i - rho0) - g) + (1 - omega/2) F_i,
-        // A_i = 1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u   (f^eq = w rho A_i),
-        // F_i = w [3 (e.F - u.F) + 9 (e.u)(e.F)].
+        //   g* = g + omega (f^eq - w rho0 - g) + (1 - omega/2) F_i,
+        //   f^eq = w rho [1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u],
+        //   F_i  = w [3 (e.F - u.F) + 9 (e.u)(e.F)],
+        // collected as g* = (1 - omega) g + w T_i with
+        //   T_i = c0 + c1 e.u + c2 (e.u)^2 + (e.F)(3 cf + 9 cf e.u),
+        //   c0 = omega rho (1 - 1.5 u.u) - omega rho0 - 3 cf u.F,
+        //   c1 = 3 omega rho, c2 = 4.5 omega rho, cf = 1 - omega/2.
         const C a0 = (C)1 - (C)1.5 * (ux * ux + uy * uy);
         const C rho[2] = {r1, r2};
+        C c0[2], c1[2], c2[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const C wr = p.omega * rho[k];
+            const C uF = ux * Fx[k] + uy * Fy[k];
+            c0[k] = wr * a0 - p.omega_rho0[k] - p.cf3 * uF;
+            c1[k] = (C)3 * wr;
+            c2[k] = (C)4.5 * wr;
+        }
         const bool sr = (S == ST_F16 || S == ST_BF16) && (p.flags & FL_ROUND_STOCHASTIC);
         uint32_t rs = sr ? sr_seed(node, p.tick) : 0u;
         const uint32_t voff = (uint32_t)node * (uint32_t)sizeof(R);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const C uF = ux * Fx[k] + uy * Fy[k];
+        for (int i = 0; i < 9; ++i) {
+            const C w = (C)qw(i);
+            const int ex = qx(i), ey = qy(i);
+            const C eu = (C)ex * ux + (C)ey * uy;
+            const C eu2 = eu * eu;
+            const C h = p.cf3 + p.cf9 * eu;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const C w = (C)qw(i);
-                const int ex = qx(i), ey = qy(i);
-                const C eu = (C)ex * ux + (C)ey * uy;
+            for (int k = 0; k < 2; ++k) {
                 const C eF = (C)ex * Fx[k] + (C)ey * Fy[k];
-                const C geq = w * (rho[k] * (a0 + eu * ((C)3 + (C)4.5 * eu)) - p.rho0[k]);
-                const C Fi = w * ((C)3 * (eF - uF) + (C)9 * eu * eF);
-                const C gs = f[k][i] + p.omega * (geq - f[k][i]) + p.cforce * Fi;
+                const C T = (i == 0) ? c0[k] : c0[k] + c1[k] * eu + c2[k] * eu2 + h * eF;
+                const C gs = p.omw * f[k][i] + w * T;
                 R out;
                 if (S == ST_F16 || S == ST_BF16) {
                     if (sr) out = T::enc_sr(gs, lcg_next(rs));
@@ -503,6 +516,14 @@ __device__ __forceinline__ void process_unit(const KParams<typename Traits<S>::C
 {
     const PopMem<S> mr = make_mem<S>(p.A, p.N);
     const PopMem<S> mw = make_mem<S>(p.B, p.N);
+    if (p.xcd_slabs) {
+        // workgroup b runs on XCD b % 8: slab b % 8 of the rows, strip b / 8
+        const int strip = u >> 3, slab = u & 7;
+        const int y0 = (int)(((long long)slab * p.ny) >> 3);
+        const int y1 = (int)(((long long)(slab + 1) * p.ny) >> 3);
+        if (strip < p.n_strips && y1 > y0) process_segment<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring, acc);
+        return;
+    }
     if (p.band_order && n_units == p.n_strips * p.n_segs) {
         const int strip = u % p.n_strips, seg = u / p.n_strips;
         const int y0 = (int)(((long long)seg * p.ny) / p.n_segs);
@@ -536,7 +557,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const KParams<typename Traits<S>
     using C = typename Traits<S>::C;
     __shared__ PsiPair<C> ring[8][BLOCK];
     const int b = blockIdx.x;
-    const int unit = (b & 7) * per_xcd + (b >> 3);
+    const int unit = p.xcd_slabs ? b : (b & 7) * per_xcd + (b >> 3);
     RedAcc acc;
     if (unit < p.n_units) process_unit<S, BLOCK, MODE>(p, unit, p.n_units, ring, acc);
     if (MODE & M_REDUCE) {

@@ -12,7 +12,7 @@ using lbm::KParams;
 using lbm::qw;
 
 // Schedule bits of a tile (lbm_set_tile).
-enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u };
+enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u, SCHED_XCD_SLABS = 4u };
 
 // Strips are block - 4 columns wide (balanced over nx), or, with
 // SCHED_ALIGN, the widest multiple of `align_cols` columns that fits, from
@@ -35,6 +35,9 @@ inline void fill_physics(KParams<C> &p, unsigned flags, double Gc, double Gw1, d
 {
     p.omega = (C)(1.0 / tau);
     p.cforce = (C)(1.0 - 1.0 / (2.0 * tau));
+    p.omw = (C)(1.0 - 1.0 / tau);
+    p.cf3 = (C)(3.0 * (1.0 - 1.0 / (2.0 * tau)));
+    p.cf9 = (C)(9.0 * (1.0 - 1.0 / (2.0 * tau)));
     p.half = (flags & LBM_VEL_LITERAL) ? (C)0 : (C)0.5;
     p.negGc = (C)(-Gc);
     p.Gw1 = (C)Gw1;
@@ -56,7 +59,10 @@ inline void fill_physics(KParams<C> &p, unsigned flags, double Gc, double Gw1, d
     p.t3 = (C)t3;
     for (int k = 0; k < 2; ++k)
         for (int a = 0; a < 2; ++a) p.g[k][a] = (C)acc[k][a];
-    for (int k = 0; k < 2; ++k) p.rho0[k] = deviation ? (C)rho0[k] : (C)0;
+    for (int k = 0; k < 2; ++k) {
+        p.rho0[k] = deviation ? (C)rho0[k] : (C)0;
+        p.omega_rho0[k] = deviation ? (C)(rho0[k] / tau) : (C)0;
+    }
 }
 
 }  // namespace lbm_host

@@ -1,0 +1,90 @@
+"""Full-size checks on the 16384 x 2048 constriction channel, in the launch
+configuration the benchmark times (autotuned tile).
+
+The oracle cannot step the whole lattice in test time, so it checks sampled
+nodes one by one: the update of node x from t to t+1 reads only positions
+within Chebyshev distance 3 of x (pull sources at distance 1, whose forces
+read the E8 stencil at distance 2 around them), so the oracle stepped once
+on the 7 x 7 window of f(t) around x (taken from the device) must reproduce
+the device's f(x, t+1).  Whole-lattice properties (mass conservation, no
+non-finite value) are checked at full size.
+"""
+import numpy as np
+import pytest
+
+from paper_2505_22256_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def channel():
+    return W.constrictions()
+
+
+def _samples(wl, n_each=16, seed=7):
+    rng = np.random.default_rng(seed)
+    fluid = np.argwhere(wl.solid == 0)
+    # nodes next to a solid (within distance 3) exercise bounce-back,
+    # the second-layer copy and the adhesion force
+    from scipy.ndimage import binary_dilation
+    near = binary_dilation(wl.solid.astype(bool), iterations=3) & (wl.solid == 0)
+    near_idx = np.argwhere(near)
+    seam = fluid[(fluid[:, 1] < 3) | (fluid[:, 1] >= wl.nx - 3)]
+    pick = lambda a: a[rng.choice(len(a), n_each, replace=False)]
+    return np.concatenate([pick(fluid), pick(near_idx), pick(seam)])
+
+
+def _oracle_one_step(oracle_mod, wl, f_win, y0, x0, h, w):
+    ys = np.arange(y0, y0 + h)
+    xs = (x0 + np.arange(w)) % wl.nx
+    mask = wl.solid[np.ix_(ys, xs)]
+    o = oracle_mod.Oracle(w, h, 0)  # window edges are never read for the centre node
+    o.set_geometry(mask)
+    o.set_params(wl.G_c, wl.G_ads, wl.tau)
+    o.set_body_accel(*wl.accel)
+    o.set_populations(f_win)
+    o.step(1)
+    return o.get_populations()
+
+
+# Tolerances: FP32 storage and arithmetic, a few ulps of the largest
+# population (~0.45): 2e-6 relative.  FP16 storage rounds the stored
+# deviation |g| <= ~0.45 to half an FP16 ulp (2^-11 relative): 1.2e-4
+# absolute, about 3e-4 of the largest population; 5e-4 allows that.
+@pytest.mark.parametrize("storage,tol", [(1, 2e-6), (2, 5e-4)])
+def test_sampled_nodes_one_step_against_oracle(oracle_mod, lbm_mod, channel, storage, tol):
+    wl = channel
+    g = lbm_mod.lattice_from_workload(wl, storage)
+    g.autotune(2)
+    g.step(40)
+    samples = _samples(wl)
+    before = []
+    for (y, x) in samples:
+        y0 = max(0, y - 3)
+        h = min(wl.ny, y + 4) - y0
+        before.append((y0, x - 3, h, 7, g.get_populations_window(x - 3, y0, 7, h)))
+    g.step(1)
+    worst = 0.0
+    for (y, x), (y0, x0, h, w, f_win) in zip(samples, before):
+        after = g.get_populations_window(x, y, 1, 1)[:, :, 0, 0]
+        ref = _oracle_one_step(oracle_mod, wl, f_win, y0, x0, h, w)[:, :, y - y0, 3]
+        scale = np.max(np.abs(ref))
+        err = np.max(np.abs(after - ref)) / scale
+        worst = max(worst, err)
+        assert err < tol, (int(y), int(x), err)
+    print(f"storage {storage}: worst relative one-step error {worst:.2e} over {len(samples)} nodes")
+
+
+def test_full_lattice_mass_and_finiteness(lbm_mod, channel):
+    wl = channel
+    g = lbm_mod.lattice_from_workload(wl, lbm_mod.F32)
+    g.autotune(2)
+    m0 = g.reduce()
+    g.step(200)
+    m1 = g.reduce()
+    assert m1[7] == 0
+    for k in (0, 1):
+        assert abs(m1[k] - m0[k]) / m0[k] < 1e-5
+    # the body force drives both components along +x
+    assert m1[2] > 0

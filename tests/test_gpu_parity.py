@@ -181,7 +181,7 @@ def test_tiling_does_not_change_results(lbm_mod):
     wl = W.cylinder_drop(G_ads=0.1, nx=200, ny=180, R=30, centre=(100, 70), r_drop=25,
                          drop_centre=(100, 115))
     ref = None
-    for tile in ((64, 8, 0), (128, 32, 1), (256, 64, 2), (256, 7, 3), (256, 0, 0), (128, 0, 1)):
+    for tile in ((64, 8, 0), (128, 32, 1), (256, 64, 2), (256, 7, 3), (256, 0, 0), (128, 0, 1), (256, 0, 5), (64, 0, 4)):
         g = lbm_mod.lattice_from_workload(wl, lbm_mod.F32)
         g.set_tile(*tile)
         g.step(100)
