@@ -742,6 +742,52 @@ static double wall_distance(int kind, const double wall[3], double x, double y)
     return sqrt(dx * dx + dy * dy) - wall[2];
 }
 
+/* Label the 4-connected regions (links along x and y, not across the
+ * periodic seams, the same links the interface points are taken on) of
+ * fluid nodes with rho^e > 0 and of fluid nodes with rho^e <= 0, by a
+ * breadth-first flood fill in scan order.  best[1] / best[0] receive the
+ * label of the largest region of each phase (ties: the region met first in
+ * scan order, i.e. the one holding the smallest node index), -1 if none.
+ * Only the interface between these two regions, the droplet and the fluid
+ * around it, enters the fit: pockets trapped inside the droplet and
+ * satellite droplets are left out. */
+static int largest_regions(const oracle_ctx *c, const double *re, int *lab, int best[2])
+{
+    size_t n = (size_t)c->n;
+    int *queue = (int *)malloc(n * sizeof(int));
+    if (!queue) return -1;
+    for (size_t id = 0; id < n; ++id) lab[id] = -1;
+    int nlab = 0, best_size[2] = {0, 0};
+    best[0] = best[1] = -1;
+    for (int seed = 0; seed < c->n; ++seed) {
+        if (c->solid[seed] || lab[seed] >= 0) continue;
+        const int phase = re[seed] > 0.0;
+        int head = 0, tail = 0;
+        queue[tail++] = seed;
+        lab[seed] = nlab;
+        while (head < tail) {
+            const int a = queue[head++];
+            const int x = a % c->nx, y = a / c->nx;
+            const int nb[4][2] = {{x + 1, y}, {x - 1, y}, {x, y + 1}, {x, y - 1}};
+            for (int k = 0; k < 4; ++k) {
+                const int xx = nb[k][0], yy = nb[k][1];
+                if (xx < 0 || yy < 0 || xx >= c->nx || yy >= c->ny) continue;
+                const int b = yy * c->nx + xx;
+                if (c->solid[b] || lab[b] >= 0 || (re[b] > 0.0) != phase) continue;
+                lab[b] = nlab;
+                queue[tail++] = b;
+            }
+        }
+        if (tail > best_size[phase]) {
+            best_size[phase] = tail;
+            best[phase] = nlab;
+        }
+        ++nlab;
+    }
+    free(queue);
+    return 0;
+}
+
 int oracle_interface_points(oracle_ctx *c, int kind, const double wall[3], double *px, double *py,
                             int cap, int *n_out)
 {
@@ -751,12 +797,18 @@ int oracle_interface_points(oracle_ctx *c, int kind, const double wall[3], doubl
     size_t n = (size_t)c->n;
     double *r1 = (double *)malloc(n * sizeof(double)), *r2 = (double *)malloc(n * sizeof(double));
     double *re = (double *)malloc(n * sizeof(double));
-    if (!r1 || !r2 || !re) {
-        free(r1); free(r2); free(re);
+    int *lab = (int *)malloc(n * sizeof(int));
+    int best[2];
+    if (!r1 || !r2 || !re || !lab) {
+        free(r1); free(r2); free(re); free(lab);
         return fail(c, ORC_ENOMEM, "out of memory");
     }
     oracle_get_fields(c, r1, r2, NULL, NULL);
     for (size_t id = 0; id < n; ++id) re[id] = c->solid[id] ? 0.0 : (r1[id] - r2[id]) / (r1[id] + r2[id]);
+    if (largest_regions(c, re, lab, best)) {
+        free(r1); free(r2); free(re); free(lab);
+        return fail(c, ORC_ENOMEM, "out of memory");
+    }
     int count = 0;
     for (int y = 0; y < c->ny; ++y)
         for (int x = 0; x < c->nx; ++x) {
@@ -768,6 +820,7 @@ int oracle_interface_points(oracle_ctx *c, int kind, const double wall[3], doubl
                 int bnode = y2 * c->nx + x2;
                 if (c->solid[bnode]) continue;
                 if ((re[a] > 0.0) == (re[bnode] > 0.0)) continue;
+                if (lab[a] != best[re[a] > 0.0] || lab[bnode] != best[re[bnode] > 0.0]) continue;
                 double tpar = re[a] / (re[a] - re[bnode]);
                 double qx = x + tpar * (x2 - x), qy = y + tpar * (y2 - y);
                 if (wall_distance(kind, wall, qx, qy) < 3.0) continue;
@@ -778,7 +831,7 @@ int oracle_interface_points(oracle_ctx *c, int kind, const double wall[3], doubl
                 ++count;
             }
         }
-    free(r1); free(r2); free(re);
+    free(r1); free(r2); free(re); free(lab);
     if (n_out) *n_out = count;
     return ORC_OK;
 }

@@ -73,7 +73,13 @@ long oracle_time(const oracle_ctx *c);
 int oracle_get_fields(oracle_ctx *c, double *rho1, double *rho2, double *ux, double *uy);
 /* M1, M2, Px, Py, max|u|, min rho1, max rho1, count of non-finite nodes */
 int oracle_reduce(oracle_ctx *c, double out[8]);
-/* wall_kind 0: flat wall below the drop, wall[0] = wall line y_w.
+/* Contact angle (the paper gives no measuring method): points where
+ * rho^e = (rho1 - rho2)/(rho1 + rho2) changes sign along an x or y link of
+ * two fluid nodes, placed by linear interpolation, kept when the link joins
+ * the largest rho^e > 0 region to the largest rho^e <= 0 region (4-connected,
+ * not across periodic seams) and the point lies at least 3 lattice units
+ * from the wall; circle fit; angle measured through component 1.
+ * wall_kind 0: flat wall below the drop, wall[0] = wall line y_w.
  * wall_kind 1: cylinder, wall[0..1] = centre, wall[2] = surface radius. */
 int oracle_contact_angle(oracle_ctx *c, int wall_kind, const double wall[3], double *theta_deg);
 int oracle_interface_points(oracle_ctx *c, int wall_kind, const double wall[3],

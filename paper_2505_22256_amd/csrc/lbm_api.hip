@@ -628,11 +628,17 @@ int lbm_contact_angle(lbm_ctx *c, int wall_kind, const double wall[3], double *t
     } args_h = {{dims_h[0], dims_h[1]}, off_h, wd};
     Args *d_args = nullptr;
     HIPCHK(c, hipMalloc(&d_args, sizeof(Args)));
+    // region labels in the velocity half of the field staging (2N doubles
+    // hold 2N + 2 ints): parents, region sizes, the two chosen roots
+    int *par = (int *)(c->d_tmp + 2 * c->N), *cnt = par + c->N, *best = cnt + c->N;
     hipError_t e = hipMemcpyAsync(d_args, &args_h, sizeof(Args), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_phase_regions(c->stream, (const int *)d_args->dims, (const long long *)&d_args->off, 1,
+                                 (long long)c->N, c->d_tmp, c->d_tmp + c->N, c->d_solid, par, cnt, best);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_contact_angle, dim3(1), dim3(256), 0, c->stream, (const int *)d_args->dims,
                            (const long long *)&d_args->off, c->d_tmp, c->d_tmp + c->N, c->d_solid,
-                           (const WallDesc *)&d_args->wd, c->d_out + 8);
+                           (const int *)par, (const int *)best, (const WallDesc *)&d_args->wd, c->d_out + 8);
         e = hipGetLastError();
     }
     double res[6] = {0, 0, 0, 0, 0, 0};

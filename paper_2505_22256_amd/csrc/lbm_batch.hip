@@ -9,6 +9,7 @@
 #include "lbm_kernels.hpp"
 #include "lbm_params.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -471,8 +472,15 @@ int lbm_batch_contact_angles(lbm_batch *b, double *theta_deg)
         if (rc) return rc;
     }
     const long long T = b->total_nodes;
+    long long max_nodes = 0;
+    for (const BatchRun &br : b->runs) max_nodes = std::max(max_nodes, (long long)br.nx * br.ny);
+    // region labels in the velocity half of the field staging (2T doubles
+    // hold 2T + 2 nruns ints): parents, region sizes, chosen roots per run
+    int *par = (int *)(b->d_fields + 2 * T), *cnt = par + T, *best = cnt + T;
+    BCHK(b, launch_phase_regions(b->stream, b->d_dims, b->d_offs, b->nruns, max_nodes, b->d_fields,
+                                 b->d_fields + T, b->d_solid, par, cnt, best));
     hipLaunchKernelGGL(k_contact_angle, dim3(b->nruns), dim3(256), 0, b->stream, b->d_dims, b->d_offs, b->d_fields,
-                       b->d_fields + T, b->d_solid, b->d_walls, b->d_out);
+                       b->d_fields + T, b->d_solid, (const int *)par, (const int *)best, b->d_walls, b->d_out);
     BCHK(b, hipGetLastError());
     std::vector<double> res((size_t)b->nruns * 6);
     BCHK(b, hipMemcpyAsync(res.data(), b->d_out, res.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));

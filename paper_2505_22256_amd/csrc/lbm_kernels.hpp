@@ -727,9 +727,150 @@ struct WallDesc {
     double w0, w1, w2;
 };
 
+// ---------------------------------------------------------------------------
+// Phase regions.  Fluid nodes split into rho^e > 0 and rho^e <= 0; regions
+// are 4-connected along x and y links (not across periodic seams).  Only
+// the interface between the largest region of each phase (the droplet and
+// the fluid around it) is fitted, so pockets trapped under a droplet and
+// satellite droplets do not bend the circle.  Union-find with the smaller
+// index as the root: every region's root is its smallest node, which also
+// breaks ties between equally large regions.  Grid: blockIdx.y = run,
+// blockIdx.x strides over the run's nodes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool phase_positive(const double *r1, const double *r2, long long a)
+{
+    return (r1[a] - r2[a]) / (r1[a] + r2[a]) > 0.0;
+}
+
+static __global__ void __launch_bounds__(256)
+k_cc_init(const int *__restrict__ dims, const long long *__restrict__ offs, const uint8_t *__restrict__ solid,
+          int *__restrict__ par, int *__restrict__ cnt)
+{
+    const int run = blockIdx.y;
+    const long long N = (long long)dims[2 * run] * dims[2 * run + 1], off = offs[run];
+    for (long long a = (long long)blockIdx.x * 256 + threadIdx.x; a < N; a += (long long)gridDim.x * 256) {
+        par[off + a] = solid[off + a] ? -1 : (int)a;
+        cnt[off + a] = 0;
+    }
+}
+
+// Root of x.  Loads are device-coherent because other lanes link roots
+// concurrently; parents only ever point to smaller indices, so the walk ends.
+__device__ __forceinline__ int cc_find(int *par, int x)
+{
+    for (;;) {
+        const int p = __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+// Link the larger root under the smaller.  A failed compare-and-swap means
+// another lane linked that root first; every retry follows a successful link
+// elsewhere, so the loop ends.
+__device__ __forceinline__ void cc_unite(int *par, int a, int b)
+{
+    for (;;) {
+        const int ra = cc_find(par, a), rb = cc_find(par, b);
+        if (ra == rb) return;
+        const int hi = ra > rb ? ra : rb, lo = ra > rb ? rb : ra;
+        if (atomicCAS(par + hi, hi, lo) == hi) return;
+    }
+}
+
+static __global__ void __launch_bounds__(256)
+k_cc_hook(const int *__restrict__ dims, const long long *__restrict__ offs, const double *__restrict__ rho1,
+          const double *__restrict__ rho2, const uint8_t *__restrict__ solid, int *par_all)
+{
+    const int run = blockIdx.y, nx = dims[2 * run], ny = dims[2 * run + 1];
+    const long long N = (long long)nx * ny, off = offs[run];
+    const double *r1 = rho1 + off, *r2 = rho2 + off;
+    const uint8_t *sd = solid + off;
+    int *par = par_all + off;
+    for (long long a = (long long)blockIdx.x * 256 + threadIdx.x; a < N; a += (long long)gridDim.x * 256) {
+        if (sd[a]) continue;
+        const int x = (int)(a % nx), y = (int)(a / nx);
+        const bool pa = phase_positive(r1, r2, a);
+        if (x + 1 < nx && !sd[a + 1] && phase_positive(r1, r2, a + 1) == pa) cc_unite(par, (int)a, (int)a + 1);
+        if (y + 1 < ny && !sd[a + nx] && phase_positive(r1, r2, a + nx) == pa)
+            cc_unite(par, (int)a, (int)(a + nx));
+    }
+}
+
+// After hooking: par[a] <- root(a) for every fluid node, and region sizes.
+static __global__ void __launch_bounds__(256)
+k_cc_count(const int *__restrict__ dims, const long long *__restrict__ offs, const uint8_t *__restrict__ solid,
+           int *par_all, int *cnt_all)
+{
+    const int run = blockIdx.y;
+    const long long N = (long long)dims[2 * run] * dims[2 * run + 1], off = offs[run];
+    int *par = par_all + off, *cnt = cnt_all + off;
+    for (long long a = (long long)blockIdx.x * 256 + threadIdx.x; a < N; a += (long long)gridDim.x * 256) {
+        if (solid[off + a]) continue;
+        int r = (int)a;
+        while (par[r] != r) r = par[r];
+        par[a] = r;
+        atomicAdd(cnt + r, 1);
+    }
+}
+
+// One workgroup per run: best[2 run + phase] = root of the largest region of
+// that phase (ties: the smaller root), -1 when the phase is absent.
+static __global__ void __launch_bounds__(256)
+k_cc_pick(const int *__restrict__ dims, const long long *__restrict__ offs, const double *__restrict__ rho1,
+          const double *__restrict__ rho2, const uint8_t *__restrict__ solid, const int *__restrict__ par_all,
+          const int *__restrict__ cnt_all, int *__restrict__ best)
+{
+    __shared__ unsigned long long sh[2][256];
+    const int run = blockIdx.x, t = threadIdx.x;
+    const long long N = (long long)dims[2 * run] * dims[2 * run + 1], off = offs[run];
+    const int *par = par_all + off, *cnt = cnt_all + off;
+    unsigned long long key[2] = {0ull, 0ull};
+    for (long long a = t; a < N; a += 256) {
+        if (solid[off + a] || par[a] != (int)a) continue;
+        const int ph = phase_positive(rho1 + off, rho2 + off, a) ? 1 : 0;
+        const unsigned long long k = ((unsigned long long)(unsigned)cnt[a] << 32) | (0xffffffffull - (unsigned long long)a);
+        if (k > key[ph]) key[ph] = k;
+    }
+    sh[0][t] = key[0];
+    sh[1][t] = key[1];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int q = 0; q < 2; ++q)
+                if (sh[q][t + h] > sh[q][t]) sh[q][t] = sh[q][t + h];
+        __syncthreads();
+    }
+    if (t < 2) {
+        const unsigned long long k = sh[t][0];
+        best[2 * run + t] = k ? (int)(0xffffffffull - (k & 0xffffffffull)) : -1;
+    }
+}
+
+// Host side: label the phase regions of nruns runs (node counts up to
+// max_nodes) and pick the largest of each phase; par and cnt hold one int
+// per node at the runs' offsets, best two ints per run.
+static inline hipError_t launch_phase_regions(hipStream_t st, const int *dims, const long long *offs, int nruns,
+                                              long long max_nodes, const double *rho1, const double *rho2,
+                                              const uint8_t *solid, int *par, int *cnt, int *best)
+{
+    long long bx = (max_nodes + 255) / 256;
+    const long long cap = nruns > 1 ? 128 : 2048;
+    if (bx > cap) bx = cap;
+    if (bx < 1) bx = 1;
+    const dim3 grid((unsigned)bx, (unsigned)nruns);
+    hipLaunchKernelGGL(k_cc_init, grid, dim3(256), 0, st, dims, offs, solid, par, cnt);
+    hipLaunchKernelGGL(k_cc_hook, grid, dim3(256), 0, st, dims, offs, rho1, rho2, solid, par);
+    hipLaunchKernelGGL(k_cc_count, grid, dim3(256), 0, st, dims, offs, solid, par, cnt);
+    hipLaunchKernelGGL(k_cc_pick, dim3((unsigned)nruns), dim3(256), 0, st, dims, offs, rho1, rho2, solid,
+                       (const int *)par, (const int *)cnt, best);
+    return hipGetLastError();
+}
+
 __device__ __forceinline__ bool interface_point(int nx, int ny, const double *r1, const double *r2,
-                                                const uint8_t *solid, const WallDesc &wd, long long a,
-                                                int dir, double &qx_, double &qy_)
+                                                const uint8_t *solid, const int *par, const int *best2,
+                                                const WallDesc &wd, long long a, int dir, double &qx_,
+                                                double &qy_)
 {
     const int x = (int)(a % nx), y = (int)(a / nx);
     const int x2 = x + (dir == 0), y2 = y + (dir == 1);
@@ -739,6 +880,7 @@ __device__ __forceinline__ bool interface_point(int nx, int ny, const double *r1
     const double ra = (r1[a] - r2[a]) / (r1[a] + r2[a]);
     const double rb = (r1[b] - r2[b]) / (r1[b] + r2[b]);
     if ((ra > 0.0) == (rb > 0.0)) return false;
+    if (par[a] != best2[ra > 0.0] || par[b] != best2[rb > 0.0]) return false;
     const double t = ra / (ra - rb);
     qx_ = x + t * (x2 - x);
     qy_ = y + t * (y2 - y);
@@ -803,7 +945,8 @@ static __device__ bool solve3(double A[3][3], double b[3], double x[3])
 static __global__ void __launch_bounds__(256)
 k_contact_angle(const int *__restrict__ dims /* nx, ny per run */, const long long *__restrict__ offs,
                 const double *__restrict__ rho1, const double *__restrict__ rho2,
-                const uint8_t *__restrict__ solid, const WallDesc *__restrict__ walls, double *out)
+                const uint8_t *__restrict__ solid, const int *__restrict__ par_all,
+                const int *__restrict__ best, const WallDesc *__restrict__ walls, double *out)
 {
     __shared__ double sh[9][256];
     __shared__ double params[4];
@@ -813,6 +956,7 @@ k_contact_angle(const int *__restrict__ dims /* nx, ny per run */, const long lo
     const long long off = offs[run];
     const double *r1 = rho1 + off, *r2 = rho2 + off;
     const uint8_t *sd = solid + off;
+    const int *par = par_all + off, *best2 = best + 2 * run;
     const WallDesc wd = walls[run];
     const long long N = (long long)nx * ny;
 
@@ -821,7 +965,7 @@ k_contact_angle(const int *__restrict__ dims /* nx, ny per run */, const long lo
     for (long long a = t; a < N; a += 256)
         for (int dir = 0; dir < 2; ++dir) {
             double qx_, qy_;
-            if (interface_point(nx, ny, r1, r2, sd, wd, a, dir, qx_, qy_)) {
+            if (interface_point(nx, ny, r1, r2, sd, par, best2, wd, a, dir, qx_, qy_)) {
                 m[0] += 1.0;
                 m[1] += qx_;
                 m[2] += qy_;
@@ -841,7 +985,7 @@ k_contact_angle(const int *__restrict__ dims /* nx, ny per run */, const long lo
     for (long long a = t; a < N; a += 256)
         for (int dir = 0; dir < 2; ++dir) {
             double qx_, qy_;
-            if (interface_point(nx, ny, r1, r2, sd, wd, a, dir, qx_, qy_)) {
+            if (interface_point(nx, ny, r1, r2, sd, par, best2, wd, a, dir, qx_, qy_)) {
                 const double u = qx_ - mx, v = qy_ - my, z = u * u + v * v;
                 k9[0] += u * u; k9[1] += u * v; k9[2] += u;
                 k9[3] += v * v; k9[4] += v;
@@ -875,7 +1019,7 @@ k_contact_angle(const int *__restrict__ dims /* nx, ny per run */, const long lo
         for (long long a = t; a < N; a += 256)
             for (int dir = 0; dir < 2; ++dir) {
                 double qx_, qy_;
-                if (interface_point(nx, ny, r1, r2, sd, wd, a, dir, qx_, qy_)) {
+                if (interface_point(nx, ny, r1, r2, sd, par, best2, wd, a, dir, qx_, qy_)) {
                     const double dx = qx_ - a0, dy = qy_ - b0;
                     const double d = __builtin_sqrt(dx * dx + dy * dy);
                     if (d == 0.0) continue;

@@ -30,6 +30,13 @@ PERIODIC_Y = 2
 RHO_MAJOR = 1.0
 RHO_MINOR = 0.03
 
+# Coexisting main / dissolved densities of the two components at G_c = 0.9
+# with the same total 1.03: c_s^2 ln(rho_m / rho_d) = G_c (rho_m - rho_d),
+# rho_m + rho_d = 1.03.  Droplets in large boxes start here; from 1.0 / 0.03
+# they would have to feed the dissolved level of the whole box and dissolve.
+RHO_MAJOR_EQ = 0.9319037248975761
+RHO_MINOR_EQ = 0.09809627510242387
+
 WALL_FLAT = 0
 WALL_CYLINDER = 1
 
@@ -68,17 +75,18 @@ def _grid(nx: int, ny: int):
     return x.astype(np.float64), y.astype(np.float64)
 
 
-def _two_phase(inside: np.ndarray, solid: np.ndarray):
+def _two_phase(inside: np.ndarray, solid: np.ndarray, major: float = RHO_MAJOR, minor: float = RHO_MINOR):
     """Component 1 dominant where ``inside``; mirrored for component 2."""
-    rho1 = np.where(inside, RHO_MAJOR, RHO_MINOR).astype(np.float64)
-    rho2 = np.where(inside, RHO_MINOR, RHO_MAJOR).astype(np.float64)
+    rho1 = np.where(inside, major, minor).astype(np.float64)
+    rho2 = np.where(inside, minor, major).astype(np.float64)
     rho1[solid != 0] = 0.0
     rho2[solid != 0] = 0.0
     return rho1, rho2
 
 
 def flat_drop(nx: int = 100, ny: int = 50, radius: float = 20.0, G_ads: float = 0.2,
-              G_c: float = 0.9, tau: float = 1.0, steps: int = 5000) -> Workload:
+              G_c: float = 0.9, tau: float = 1.0, steps: int = 5000, major: float = RHO_MAJOR,
+              minor: float = RHO_MINOR) -> Workload:
     """Semicircular droplet centred on a flat bottom wall.
 
     Solid rows y = 0 and y = ny-1, periodic in x; the droplet is
@@ -89,22 +97,25 @@ def flat_drop(nx: int = 100, ny: int = 50, radius: float = 20.0, G_ads: float = 
     solid[0, :] = 1
     solid[ny - 1, :] = 1
     inside = (x - nx / 2.0) ** 2 + (y - 0.5) ** 2 < radius * radius
-    rho1, rho2 = _two_phase(inside, solid)
+    rho1, rho2 = _two_phase(inside, solid, major, minor)
     return Workload("flat_drop", nx, ny, PERIODIC_X, solid, rho1, rho2, G_c=G_c, G_ads=G_ads,
                     tau=tau, steps=steps, wall_kind=WALL_FLAT, wall=(0.5, 0.0, 0.0))
 
 
 def cylinder_drop(G_ads: float = 0.0, nx: int = 400, ny: int = 400, R: float = 60.0,
                   centre=(200.0, 150.0), r_drop: float = 50.0, drop_centre=(200.0, 240.0),
-                  G_c: float = 0.9, tau: float = 1.0, steps: int = 20000) -> Workload:
+                  G_c: float = 0.9, tau: float = 1.0, steps: int = 20000,
+                  major: float = RHO_MAJOR_EQ, minor: float = RHO_MINOR_EQ) -> Workload:
     """Droplet on a staircase-voxelised cylinder in a fully periodic box.
 
-    Solid where (x-cx)^2 + (y-cy)^2 <= R^2; droplet (strict <) centred at
-    ``drop_centre``.  The wall surface for the angle is R + 0.5."""
+    Solid where (x-cx)^2 + (y-cy)^2 < R^2 (strict: with <= an integer R
+    leaves a one-voxel spike at each pole, a solid feature one node thick);
+    droplet (strict <) centred at ``drop_centre``.  The wall surface for the
+    angle is R + 0.5.  Starts at the coexisting densities of G_c = 0.9."""
     x, y = _grid(nx, ny)
-    solid = (((x - centre[0]) ** 2 + (y - centre[1]) ** 2) <= R * R).astype(np.uint8)
+    solid = (((x - centre[0]) ** 2 + (y - centre[1]) ** 2) < R * R).astype(np.uint8)
     inside = (x - drop_centre[0]) ** 2 + (y - drop_centre[1]) ** 2 < r_drop * r_drop
-    rho1, rho2 = _two_phase(inside, solid)
+    rho1, rho2 = _two_phase(inside, solid, major, minor)
     return Workload("cylinder_drop", nx, ny, PERIODIC_X | PERIODIC_Y, solid, rho1, rho2, G_c=G_c,
                     G_ads=G_ads, tau=tau, steps=steps, wall_kind=WALL_CYLINDER,
                     wall=(centre[0], centre[1], R + 0.5))
@@ -165,7 +176,8 @@ def calibration_runs(seed: int = 22256, nruns: int = 512, steps: int = 10000) ->
     (Bernoulli 0.5); G_ads ~ U[-0.35, 0.35]; tau ~ U[0.7, 1.2].  Droplet radius
     0.2 side.  Flat: walls at rows 0 and side-1, droplet centre (side/2, 0.5).
     Cylinder: periodic, R = 0.15 side at (side/2, 0.375 side), droplet centre
-    (side/2, 0.675 side)."""
+    (side/2, 0.675 side).  Droplets start at the coexisting densities of
+    G_c = 0.9."""
     rng = np.random.default_rng(seed)
     sides = [128, 192, 256, 384, 512]
     runs = []
@@ -179,7 +191,8 @@ def calibration_runs(seed: int = 22256, nruns: int = 512, steps: int = 10000) ->
                               centre=(side / 2.0, 0.375 * side), r_drop=0.2 * side,
                               drop_centre=(side / 2.0, 0.675 * side), tau=tau, steps=steps)
         else:
-            w = flat_drop(nx=side, ny=side, radius=0.2 * side, G_ads=G_ads, tau=tau, steps=steps)
+            w = flat_drop(nx=side, ny=side, radius=0.2 * side, G_ads=G_ads, tau=tau, steps=steps,
+                          major=RHO_MAJOR_EQ, minor=RHO_MINOR_EQ)
         w.name = "calibration"
         runs.append(w)
     return runs

@@ -298,6 +298,37 @@ def test_errors_and_call_order(lbm_mod):
     assert e.value.code == L.EUNSTABLE
 
 
+def _pocket_workload():
+    """Tanh cap on a cylinder at 110 degrees, with a component-2 pocket
+    inside the droplet next to the wall and a satellite droplet."""
+    n, R, r, C, theta = 160, 30.0, 25.0, (80.0, 60.0), 110.0
+    Rs = R + 0.5
+    d = np.sqrt(Rs * Rs + r * r - 2 * Rs * r * np.cos(np.radians(theta)))
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    solid = (((x - C[0]) ** 2 + (y - C[1]) ** 2) < R * R).astype(np.uint8)
+    s = np.tanh((r - np.hypot(x - C[0], y - C[1] - d)) / 2.0)
+    for (cx, cy, rb, sign) in ((C[0], C[1] + R + 9.0, 5.0, -1.0), (20.0, 150.0, 6.0, 1.0)):
+        sb = np.tanh((rb - np.hypot(x - cx, y - cy)) / 2.0)
+        s = np.where(sb > -0.999, sign * sb, s)
+    rho1 = np.where(solid, 0, 0.52 + 0.43 * s)
+    rho2 = np.where(solid, 0, 0.52 - 0.43 * s)
+    return W.Workload("pocket", n, n, W.PERIODIC_X | W.PERIODIC_Y, solid, rho1, rho2, G_c=0.9, G_ads=0.0,
+                      tau=1.0, wall_kind=W.WALL_CYLINDER, wall=(C[0], C[1], Rs))
+
+
+def test_contact_angle_ignores_pocket_and_satellite(oracle_mod, lbm_mod):
+    """The device labels the phase regions (union-find) and fits only the
+    interface between the largest region of each sign, as the oracle does
+    (breadth-first labelling): same angle, single context and batch."""
+    wl = _pocket_workload()
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64)
+    to = o.contact_angle(wl.wall_kind, wl.wall)
+    assert abs(to - 110.0) < 0.3
+    assert abs(g.contact_angle(wl.wall_kind, wl.wall) - to) < 1e-9
+    b = lbm_mod.Batch([W.flat_drop(nx=64, ny=40, radius=12), wl], lbm_mod.F64)
+    assert abs(b.contact_angles()[1] - to) < 1e-9
+
+
 def _small_runs():
     runs = [W.flat_drop(nx=64, ny=40, radius=12, G_ads=0.1, tau=0.8),
             W.cylinder_drop(G_ads=-0.2, nx=96, ny=90, R=14, centre=(48, 34), r_drop=18,
