@@ -40,23 +40,25 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_constrictions.json")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources that define the step kernel and its launch
+    geometry (the tile is checked separately)."""
     h = hashlib.sha256()
-    for name in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_api.hip"):
+    for name in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp"):
         with open(os.path.join(ROOT, "paper_2505_22256_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage_name: str, n_fluid: int):
+def measured_traffic(storage_name: str, tile):
     """HBM bytes per step launch from the committed rocprofv3 counter runs,
-    only while they were taken on the current kernel source."""
+    only while they were taken on the current kernel source and tile."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
     ent = rec.get(storage_name)
-    if not ent or rec.get("kernel_hash") != kernel_source_hash():
+    if not ent or rec.get("kernel_hash") != kernel_source_hash() or list(ent.get("tile", [])) != list(tile):
         return None
     return ent.get("bytes_per_launch")
 
@@ -176,7 +178,7 @@ def main():
     ms_step = ms / args.steps
     mlups = n_fluid * args.steps / (ms * 1e-3) / 1e6
     achieved = bpu * n_fluid / (ms_step * 1e-3) / 1e9
-    traffic = measured_traffic(args.storage, n_fluid)
+    traffic = measured_traffic(args.storage + ("_sr" if args.stochastic else ""), (block, rows, sched))
     lat.close()
 
     out = {

@@ -188,17 +188,21 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
 
 /* Tile shape of the step kernel: block in {64, 128, 256} threads (strip
  * width block - 4 columns) and rows per workgroup segment.  seg_rows = 0
- * (the default) is persistent scheduling: one work unit per resident
- * workgroup, each taking an equal share of the strip rows.  Results do not
+ * is persistent scheduling: one work unit per resident workgroup, each
+ * taking an equal share of the strip rows.  Default after lbm_create:
+ * block 256, seg_rows 16, sched LBM_SCHED_ALIGN | LBM_SCHED_BANDS (FP16 /
+ * BF16: LBM_SCHED_BANDS).  Results do not
  * depend on the tile shape (bitwise).  sched bits: LBM_SCHED_ALIGN makes
  * strips a multiple of 128 bytes wide from x = 0, so that stores never
  * cover part of a cache line shared with another workgroup;
  * LBM_SCHED_BANDS (fixed segments only) runs units across the strips
  * first, so concurrent workgroups cover whole rows; LBM_SCHED_XCD_SLABS
  * gives each of the 8 XCDs one contiguous slab of rows, one workgroup per
- * strip marching down it (seg_rows is ignored).  lbm_autotune times the candidates
- * for `steps` steps each on the current state (restoring it afterwards)
- * and keeps the fastest. */
+ * strip marching down it (seg_rows is ignored).  lbm_autotune times the
+ * current tile and then every candidate for `steps` steps each on the
+ * current state (restoring state and time afterwards); a candidate replaces
+ * the best so far only when it is at least 2 % faster, so timing noise does
+ * not move the choice between near-equal tiles. */
 int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched);
 int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows, unsigned *sched);
 int lbm_autotune(lbm_ctx *c, int steps);

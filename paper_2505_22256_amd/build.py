@@ -15,8 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "lbm_batch.hip")]
-HEADERS = [os.path.join(CSRC, "lbm_device.hpp"), os.path.join(CSRC, "lbm_kernels.hpp"),
-           os.path.join(ROOT, "include", "lbm.h")]
+HEADERS = [os.path.join(CSRC, n) for n in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp",
+                                            "lbm_contact.hpp")] + [os.path.join(ROOT, "include", "lbm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

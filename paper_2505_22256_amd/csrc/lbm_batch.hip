@@ -6,6 +6,7 @@
 // result is bitwise that of a single context.  Optionally a HIP graph of
 // several steps is captured once and replayed.
 #include "lbm.h"
+#include "lbm_contact.hpp"
 #include "lbm_kernels.hpp"
 #include "lbm_params.hpp"
 
