@@ -112,6 +112,61 @@ def precision_check(steps: int = 5000):
                               for k, v in th.items() if k != "f64"}}
 
 
+def calibration_batch(args):
+    """The 512-run contact-angle calibration batch (seed 22256): square
+    lattices of side 128..512, flat or cylinder walls, per-run G_ads and tau,
+    one launch per step over all runs, HIP graph replays, autotuned tile.
+    With --full, runs the configured 10000 steps and reports the angles
+    (and their difference from the FP64 oracle values stored for the first
+    16 runs)."""
+    import torch
+    runs = W.calibration_runs()
+    storage = STORAGES[args.storage]
+    flags = lbm.ROUND_STOCHASTIC if args.stochastic else 0
+    for wl in runs:
+        wl.flags |= flags
+    stream = torch.cuda.Stream()
+    b = lbm.Batch(runs, storage)
+    b.set_stream(stream.cuda_stream)
+    tile = b.autotune(2)
+    b.use_graph(True, 50)
+    n_fluid = b.fluid_nodes
+    steps = runs[0].steps if args.full else args.steps
+    warm = 0 if args.full else args.warmup
+    with torch.cuda.stream(stream):
+        b.step(warm)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        b.step(steps)
+        ev1.record(stream)
+        ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    mlups = n_fluid * steps / (ms * 1e-3) / 1e6
+    out = {"metric": "calibration batch MLUPS (fluid-node updates per second over all runs)",
+           "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": steps, "warmup": warm,
+           "ms_per_step": round(ms / steps, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if storage == lbm.F64 else "f32", "data": "synthetic",
+           "config": {"workload": f"calibration batch: {len(runs)} runs, sides 128..512, flat/cylinder, "
+                                  f"seed 22256, {args.storage} storage" + (" stochastic rounding" if args.stochastic else ""),
+                      "runs": len(runs), "fluid_nodes": n_fluid, "tile": {"block": tile[0], "seg_rows": tile[1]},
+                      "graph_steps": 50}}
+    if args.full:
+        th = b.contact_angles()
+        out["theta_deg"] = {"finite": int(np.isfinite(th).sum()), "min": float(np.nanmin(th)),
+                            "max": float(np.nanmax(th))}
+        gold = os.path.join(ROOT, "tests", "golden", "calibration_theta.json")
+        if os.path.exists(gold):
+            with open(gold) as f:
+                ref = json.load(f)["runs"]
+            errs = [abs(th[r["index"]] - r["theta_deg"]) for r in ref if r["theta_deg"] is not None]
+            out["theta_vs_oracle_first_runs"] = {"runs": len(errs), "max_abs_err_deg": round(max(errs), 4),
+                                                 "mean_abs_err_deg": round(float(np.mean(errs)), 4)}
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +178,10 @@ def main():
     ap.add_argument("--tile", default="auto", help="auto or BLOCK,ROWS[,SCHED]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--workload", default="constrictions", choices=["constrictions", "calibration"],
+                    help="constrictions: the 16384x2048 channel (default); calibration: the 512-run batch")
+    ap.add_argument("--full", action="store_true", help="calibration: run the configured 10000 steps and "
+                    "report contact angles")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (read BYTES, write BYTES) five "
                          "times, to scale HBM byte counters against a known traffic")
@@ -143,6 +202,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "calibration":
+        calibration_batch(args)
+        return
 
     import torch  # device streams and events only
 

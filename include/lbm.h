@@ -245,6 +245,13 @@ typedef struct {
  * inputs and tile shape. */
 int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int storage);
 int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows);
+/* Tile of the batched kernel by measurement: times the current tile and
+ * then block in {64, 128, 256} x seg_rows in {8, ..., 256} for `steps`
+ * steps each (one launch per step, no graph), keeps the fastest (a
+ * candidate needs a 2 % margin over the best so far) and restores every
+ * run's state and the step counter.  Synchronous. */
+int lbm_batch_autotune(lbm_batch *b, int steps);
+int lbm_batch_get_tile(const lbm_batch *b, int *block, int *seg_rows);
 int lbm_batch_step(lbm_batch *b, int n);
 int lbm_batch_use_graph(lbm_batch *b, int use_graph, int steps_per_graph);
 int lbm_batch_get_fields(lbm_batch *b, int run, double *rho1, double *rho2, double *ux, double *uy);

@@ -414,6 +414,73 @@ int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows)
     return upload_params(b);
 }
 
+int lbm_batch_autotune(lbm_batch *b, int steps)
+{
+    if (!b) return LBM_EINVAL;
+    if (steps < 1) return berr(b, LBM_EINVAL, "steps must be >= 1");
+    BCHK(b, hipStreamSynchronize(b->stream));
+    const size_t bytes = (size_t)b->total_nodes * 18 * esize(b->storage);
+    const int flip0 = b->flip;
+    unsigned tick0 = 0;
+    BCHK(b, hipMemcpy(&tick0, b->d_tick, sizeof tick0, hipMemcpyDeviceToHost));
+    void *backup = nullptr;
+    if (hipMalloc(&backup, bytes) != hipSuccess) return berr(b, LBM_ENOMEM, "autotune backup allocation failed");
+    hipError_t e = hipMemcpyAsync(backup, b->buf[flip0], bytes, hipMemcpyDeviceToDevice, b->stream);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&ev0);
+    if (e == hipSuccess) e = hipEventCreate(&ev1);
+    const int blocks[3] = {64, 128, 256};
+    const int rows[6] = {8, 16, 32, 64, 128, 256};
+    const int cur_b = b->block, cur_r = b->seg_rows;
+    int best_b = cur_b, best_r = cur_r, rc = LBM_OK;
+    float best_ms = 1e30f;
+    // candidate -1 is the incumbent tile; the rest need a 2 % margin to win
+    for (int cand = -1; cand < 3 * 6 && e == hipSuccess && rc == LBM_OK; ++cand) {
+        const int cb = cand < 0 ? cur_b : blocks[cand / 6], cr = cand < 0 ? cur_r : rows[cand % 6];
+        b->block = cb;
+        b->seg_rows = cr;
+        rc = upload_params(b);
+        if (rc) break;
+        e = launch_batch(b, b->flip);  // warm-up
+        b->flip ^= 1;
+        if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
+        for (int s = 0; s < steps && e == hipSuccess; ++s) {
+            e = launch_batch(b, b->flip);
+            b->flip ^= 1;
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (e == hipSuccess && (cand < 0 || ms < 0.98f * best_ms)) {
+            best_ms = ms;
+            best_b = cb;
+            best_r = cr;
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b->buf[flip0], backup, bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_tick, &tick0, sizeof tick0, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFree(backup);
+    b->flip = flip0;
+    b->block = best_b;
+    b->seg_rows = best_r;
+    const int rc2 = upload_params(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return berr(b, LBM_EDEVICE, "batch autotune failed: %s", hipGetErrorString(e));
+    return rc2;
+}
+
+int lbm_batch_get_tile(const lbm_batch *b, int *block, int *seg_rows)
+{
+    if (!b || !block || !seg_rows) return LBM_EINVAL;
+    *block = b->block;
+    *seg_rows = b->seg_rows;
+    return LBM_OK;
+}
+
 int lbm_batch_use_graph(lbm_batch *b, int use_graph, int steps_per_graph)
 {
     if (!b) return LBM_EINVAL;

@@ -72,6 +72,8 @@ SIGNATURES = {
     "lbm_destroy": (None, [_P]),
     "lbm_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(LbmRunDesc), _I]),
     "lbm_batch_set_tile": (_I, [_P, _I, _I]),
+    "lbm_batch_autotune": (_I, [_P, _I]),
+    "lbm_batch_get_tile": (_I, [_P, _P, _P]),
     "lbm_batch_step": (_I, [_P, _I]),
     "lbm_batch_use_graph": (_I, [_P, _I, _I]),
     "lbm_batch_get_fields": (_I, [_P, _I, _P, _P, _P, _P]),
@@ -316,6 +318,17 @@ class Batch:
 
     def set_tile(self, block, seg_rows):
         self._c(self._L.lbm_batch_set_tile(self.h, block, seg_rows))
+
+    def get_tile(self):
+        b, r = _I(), _I()
+        self._c(self._L.lbm_batch_get_tile(self.h, ctypes.byref(b), ctypes.byref(r)))
+        return b.value, r.value
+
+    def autotune(self, steps=3):
+        """Time the tile candidates on the current state (restored after)
+        and keep the fastest; returns (block, seg_rows)."""
+        self._c(self._L.lbm_batch_autotune(self.h, int(steps)))
+        return self.get_tile()
 
     def use_graph(self, on=True, steps_per_graph=100):
         self._c(self._L.lbm_batch_use_graph(self.h, 1 if on else 0, steps_per_graph))
