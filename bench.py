@@ -167,6 +167,71 @@ def calibration_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def saturation_and_front(wl, rho1, rho2):
+    """Saturation S1 = fraction of fluid nodes with rho^e > 0, and front
+    X_f = last column of the run of columns from x = 0 whose fluid nodes have
+    rho^e > 0 for at least half (the channel is periodic in x, so component
+    1 that leaks backwards across the seam does not count as the front)."""
+    fluid = wl.solid == 0
+    pos = fluid & (rho1 > rho2)
+    s1 = float(pos.sum()) / float(fluid.sum())
+    nf = fluid.sum(axis=0)
+    frac = np.where(nf > 0, pos.sum(axis=0) / np.maximum(nf, 1), 1.0)
+    low = np.nonzero(frac < 0.5)[0]
+    return s1, int(low[0]) - 1 if len(low) else wl.nx - 1
+
+
+def porous_precision(args):
+    """Immiscible displacement in the 2048x1024 porous channel (seed 2505):
+    every storage runs the configured steps, recording saturation and front
+    every `--record-every` steps, compared with the FP64 device run (which
+    the oracle anchors in the GPU tests)."""
+    import torch
+    wl = W.porous()
+    steps = args.steps if args.steps_given else wl.steps
+    every = args.record_every
+    cases = [("f64", lbm.F64, 0), ("f32", lbm.F32, 0), ("f16", lbm.F16, 0),
+             ("f16_sr", lbm.F16, lbm.ROUND_STOCHASTIC), ("bf16", lbm.BF16, 0),
+             ("bf16_sr", lbm.BF16, lbm.ROUND_STOCHASTIC)]
+    hist, rate = {}, {}
+    stream = torch.cuda.Stream()
+    for name, st, fl in cases:
+        g = lbm.lattice_from_workload(wl, st, fl)
+        g.set_stream(stream.cuda_stream)
+        g.autotune(2)
+        rec, t_gpu = [], 0.0
+        for t in range(0, steps, every):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            g.step(every)
+            ev1.record(stream)
+            ev1.synchronize()
+            t_gpu += ev0.elapsed_time(ev1)
+            r1, r2, _, _ = g.get_fields()
+            rec.append(saturation_and_front(wl, r1, r2))
+        hist[name] = rec
+        rate[name] = round(g.fluid_nodes * steps / (t_gpu * 1e-3) / 1e6, 1)
+        g.close()
+        print(f"[porous] {name}: S1 {rec[-1][0]:.5f} front {rec[-1][1]} ({rate[name]} MLUPS)", file=sys.stderr,
+              flush=True)
+    ref = hist["f64"]
+    out = {"metric": "porous displacement: saturation and front vs FP64", "workload":
+           f"porous 2048x1024 (seed 2505, {len(wl.disks)} disks, porosity "
+           f"{1 - wl.solid[:, 96:].mean():.3f}), component 1 driven by 1e-6 from x < 64, {steps} steps, "
+           f"recorded every {every}", "fluid_nodes": wl.n_fluid,
+           "f64_final": {"S1": ref[-1][0], "front_x": ref[-1][1]}, "storages": {}}
+    for name, rec in hist.items():
+        if name == "f64":
+            continue
+        ds = max(abs(a[0] - b[0]) for a, b in zip(rec, ref))
+        dx = max(abs(a[1] - b[1]) for a, b in zip(rec, ref))
+        out["storages"][name] = {"max_abs_dS1": round(ds, 6), "max_abs_dfront": dx, "MLUPS": rate[name]}
+    out["f64_MLUPS"] = rate["f64"]
+    out["history"] = {k: [[round(a, 6), b] for a, b in v] for k, v in hist.items()}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,8 +243,10 @@ def main():
     ap.add_argument("--tile", default="auto", help="auto or BLOCK,ROWS[,SCHED]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--workload", default="constrictions", choices=["constrictions", "calibration"],
-                    help="constrictions: the 16384x2048 channel (default); calibration: the 512-run batch")
+    ap.add_argument("--workload", default="constrictions", choices=["constrictions", "calibration", "porous"],
+                    help="constrictions: the 16384x2048 channel (default); calibration: the 512-run batch; "
+                         "porous: the storage precision study")
+    ap.add_argument("--record-every", type=int, default=1000, help="porous: recording interval")
     ap.add_argument("--full", action="store_true", help="calibration: run the configured 10000 steps and "
                     "report contact angles")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -203,8 +270,12 @@ def main():
               "decomposition is a design, not part of this build.", file=sys.stderr)
         sys.exit(2)
 
+    args.steps_given = any(a.startswith("--steps") for a in sys.argv[1:])
     if args.workload == "calibration":
         calibration_batch(args)
+        return
+    if args.workload == "porous":
+        porous_precision(args)
         return
 
     import torch  # device streams and events only

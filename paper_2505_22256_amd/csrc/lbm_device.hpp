@@ -70,6 +70,11 @@ __host__ __device__ constexpr double e8w(int e2)
 }
 __host__ __device__ constexpr double e8wn(int n) { return e8w(sx(n) * sx(n) + sy(n) * sy(n)); }
 
+// Reciprocal in the compute type: exact division in FP64; the hardware
+// reciprocal (1 ulp) in FP32.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ---------------------------------------------------------------------------
 // Storage traits: raw element type, compute type, sentinel, codec
 // ---------------------------------------------------------------------------
@@ -247,8 +252,9 @@ template <class C> struct KParams {
 };
 
 // Counter-based random bits for stochastic rounding: a murmur3-style
-// finaliser of (node, step) seeds a 32-bit LCG that yields one word per
-// stored population.
+// finaliser of (node, step) seeds Marsaglia's xorshift32 (shifts 13, 17,
+// 5), whose every 32-bit word feeds the two components of one direction
+// (low and high half).  Shifts and xors only: no multiply per draw.
 __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
@@ -260,12 +266,14 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x)
 }
 __device__ __forceinline__ uint32_t sr_seed(int node, unsigned tick)
 {
-    return mix32((uint32_t)node ^ mix32(tick * 0x9e3779b9u + 0x632be5abu));
+    return mix32((uint32_t)node ^ mix32(tick * 0x9e3779b9u + 0x632be5abu)) | 1u;  // xorshift state != 0
 }
-__device__ __forceinline__ uint32_t lcg_next(uint32_t &s)
+__device__ __forceinline__ uint32_t xorshift32(uint32_t &s)
 {
-    s = s * 1664525u + 1013904223u;
-    return s >> 16;
+    s ^= s << 13;
+    s ^= s >> 17;
+    s ^= s << 5;
+    return s;
 }
 
 // Position along one axis with its two neighbours, after periodic wrapping;

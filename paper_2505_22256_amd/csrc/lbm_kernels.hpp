@@ -335,10 +335,12 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
     Fx[1] += (fdens ? (C)1 : r2) * p.g[1][0];
     Fy[1] += (fdens ? (C)1 : r2) * p.g[1][1];
 
-    // common velocity (Eq. 5 with the half-force shift of Guo's scheme)
+    // common velocity (Eq. 5 with the half-force shift of Guo's scheme);
+    // one reciprocal of the total density serves both components
     const C rt = r1 + r2;
-    const C ux = ((jx[0] + p.half * Fx[0]) + (jx[1] + p.half * Fx[1])) / rt;
-    const C uy = ((jy[0] + p.half * Fy[0]) + (jy[1] + p.half * Fy[1])) / rt;
+    const C irt = recip(rt);
+    const C ux = ((jx[0] + p.half * Fx[0]) + (jx[1] + p.half * Fx[1])) * irt;
+    const C uy = ((jy[0] + p.half * Fy[0]) + (jy[1] + p.half * Fy[1])) * irt;
 
     if (MODE & M_FIELDS) {
         p.out_rho1[node] = (double)r1;
@@ -373,6 +375,10 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         //   T_i = c0 + c1 e.u + c2 (e.u)^2 + (e.F)(3 cf + 9 cf e.u),
         //   c0 = omega rho (1 - 1.5 u.u) - omega rho0 - 3 cf u.F,
         //   c1 = 3 omega rho, c2 = 4.5 omega rho, cf = 1 - omega/2.
+        // Opposite directions share e.u and e.F up to sign, so each pair
+        // (i, opp(i)) evaluates the even part E = c0 + c2 (e.u)^2 + 9 cf
+        // (e.u)(e.F) and the odd part O = c1 e.u + 3 cf e.F once:
+        // T_i = E + O, T_opp(i) = E - O.
         const C a0 = (C)1 - (C)1.5 * (ux * ux + uy * uy);
         const C rho[2] = {r1, r2};
         C c0[2], c1[2], c2[2];
@@ -387,24 +393,40 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         const bool sr = (S == ST_F16 || S == ST_BF16) && (p.flags & FL_ROUND_STOCHASTIC);
         uint32_t rs = sr ? sr_seed(node, p.tick) : 0u;
         const uint32_t voff = (uint32_t)node * (uint32_t)sizeof(R);
+        C gs[2][9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
+        for (int k = 0; k < 2; ++k) gs[k][0] = p.omw * f[k][0] + (C)qw(0) * c0[k];
+#pragma unroll
+        for (int pair = 0; pair < 4; ++pair) {
+            const int i = pair < 2 ? pair + 1 : pair + 3;  // 1, 2, 5, 6; partners 3, 4, 7, 8
+            const int o = opp(i);
             const C w = (C)qw(i);
             const int ex = qx(i), ey = qy(i);
-            const C eu = (C)ex * ux + (C)ey * uy;
+            const C eu = ex == 0 ? (C)ey * uy : (ey == 0 ? (C)ex * ux : (C)ex * ux + (C)ey * uy);
             const C eu2 = eu * eu;
-            const C h = p.cf3 + p.cf9 * eu;
+            const C h9 = p.cf9 * eu;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const C eF = (C)ex * Fx[k] + (C)ey * Fy[k];
-                const C T = (i == 0) ? c0[k] : c0[k] + c1[k] * eu + c2[k] * eu2 + h * eF;
-                const C gs = p.omw * f[k][i] + w * T;
+                const C eF = ex == 0 ? (C)ey * Fy[k] : (ey == 0 ? (C)ex * Fx[k] : (C)ex * Fx[k] + (C)ey * Fy[k]);
+                const C E = (c0[k] + c2[k] * eu2) + h9 * eF;
+                const C O = c1[k] * eu + p.cf3 * eF;
+                gs[k][i] = p.omw * f[k][i] + w * (E + O);
+                gs[k][o] = p.omw * f[k][o] + w * (E - O);
+            }
+        }
+        // stores in direction order; with stochastic rounding one random
+        // word per direction, low half for component 1, high for component 2
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const uint32_t rw = sr ? xorshift32(rs) : 0u;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
                 R out;
                 if (S == ST_F16 || S == ST_BF16) {
-                    if (sr) out = T::enc_sr(gs, lcg_next(rs));
-                    else out = T::enc(gs);
+                    if (sr) out = T::enc_sr(gs[k][i], k == 0 ? rw : rw >> 16);
+                    else out = T::enc(gs[k][i]);
                 } else {
-                    out = T::enc(gs);
+                    out = T::enc(gs[k][i]);
                 }
                 pop_store<S>(mw, k, i, voff, out);
             }
@@ -445,10 +467,13 @@ __device__ void block_reduce_write(RedAcc acc, double *out)
         for (int q = 0; q < 8; ++q) out[q] = red[q][0];
 }
 
-// March down rows [y0, y1) of one strip.  Each iteration processes the row
-// whose loads were issued one iteration earlier (psi into the ring), issues
-// the loads of the next row, synchronises once and finishes row y; the
-// populations of rows y, y+1 and y+2 stay in registers.
+// One segment: rows [y0, y1) of a strip.  The psi of rows y0-2 .. y1+1
+// passes through the LDS ring; each iteration processes row y+2 (moments,
+// psi), issues the loads of row y+3, synchronises once and finishes row y;
+// the populations of rows y, y+1 and y+2 stay in registers.  Rows past y1+1
+// are never loaded.  (Deeper prefetch, three raw rows in flight, measured
+// slower for every storage: the extra registers cost more occupancy than
+// the latency it hides.)
 template <int S, int BLOCK, int MODE>
 __device__ __forceinline__ void process_segment(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mr,
                                                 const PopMem<S> &mw, int strip, int y0, int y1,
@@ -469,6 +494,7 @@ __device__ __forceinline__ void process_segment(const KParams<typename Traits<S>
     const bool interior = tid >= 2 && tid < w + 2;
     const Axis cx = make_axis(x0 - 2 + tid, p.nx, p.flags & FL_PERIODIC_X);
     const bool col_ok = active && cx.ok;
+    const int last = y1 + 1;  // last row whose psi is needed
 
     RowState<C> ra, rb, rc;
     RawRow<S> q;
@@ -485,19 +511,19 @@ __device__ __forceinline__ void process_segment(const KParams<typename Traits<S>
     for (;;) {
         if (y >= y1) break;
         process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rc);
-        issue_row<S>(p, mr, cx, col_ok, y + 3, q);
+        if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
         if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, ra, ring, acc);
         ++y;
         if (y >= y1) break;
         process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, ra);
-        issue_row<S>(p, mr, cx, col_ok, y + 3, q);
+        if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
         if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, rb, ring, acc);
         ++y;
         if (y >= y1) break;
         process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rb);
-        issue_row<S>(p, mr, cx, col_ok, y + 3, q);
+        if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
         if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, rc, ring, acc);
         ++y;

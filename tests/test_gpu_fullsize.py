@@ -1,5 +1,6 @@
 """Full-size checks on the 16384 x 2048 constriction channel, in the launch
-configuration the benchmark times (autotuned tile).
+configuration the benchmark times (autotuned tile), and on the 2048 x 1024
+porous channel of the precision study (FP64, anchored at t = 1000).
 
 The oracle cannot step the whole lattice in test time, so it checks sampled
 nodes one by one: the update of node x from t to t+1 reads only positions
@@ -74,6 +75,30 @@ def test_sampled_nodes_one_step_against_oracle(oracle_mod, lbm_mod, channel, sto
         worst = max(worst, err)
         assert err < tol, (int(y), int(x), err)
     print(f"storage {storage}: worst relative one-step error {worst:.2e} over {len(samples)} nodes")
+
+
+def test_porous_fp64_anchor_at_1000_steps(oracle_mod, lbm_mod):
+    """The FP64 device run that the precision study compares the reduced
+    storages with: after 1000 steps on the porous channel (14 % of fluid
+    nodes near a wall), sampled nodes advance one more step exactly as the
+    oracle advances their 7 x 7 windows (1e-12 relative)."""
+    wl = W.porous()
+    g = lbm_mod.lattice_from_workload(wl, lbm_mod.F64)
+    g.autotune(1)
+    g.step(1000)
+    samples = _samples(wl, n_each=24, seed=11)
+    before = []
+    for (y, x) in samples:
+        y0 = max(0, y - 3)
+        h = min(wl.ny, y + 4) - y0
+        before.append((y0, x - 3, h, 7, g.get_populations_window(x - 3, y0, 7, h)))
+    g.step(1)
+    for (y, x), (y0, x0, h, w, f_win) in zip(samples, before):
+        after = g.get_populations_window(x, y, 1, 1)[:, :, 0, 0]
+        ref = _oracle_one_step(oracle_mod, wl, f_win, y0, x0, h, w)[:, :, y - y0, 3]
+        assert np.max(np.abs(after - ref)) <= 1e-12 * np.max(np.abs(ref)), (int(y), int(x))
+    m = g.reduce()
+    assert m[7] == 0
 
 
 def test_full_lattice_mass_and_finiteness(lbm_mod, channel):
