@@ -244,6 +244,8 @@ typedef struct {
  * Each run's result is bitwise that of a single context with the same
  * inputs and tile shape. */
 int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int storage);
+/* (LBM_ROUND_STOCHASTIC must be set on all runs of a batch or on none:
+ * LBM_EINVAL otherwise.) */
 int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows);
 /* Tile of the batched kernel by measurement: times the current tile and
  * then block in {64, 128, 256} x seg_rows in {8, ..., 256} for `steps`

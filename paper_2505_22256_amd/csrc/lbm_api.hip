@@ -202,9 +202,22 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
     p.tab_nw = nw;
     p.tab_src = src;
     hipError_t e = hipSuccess;
+    constexpr bool narrow = S == ST_F16 || S == ST_BF16;
+    const bool sr = narrow && (c->flags & LBM_ROUND_STOCHASTIC);
     switch (pass) {
-    case P_STEP: e = launch_step_b<S, M_STORE>(p, block, c->stream); break;
-    case P_STEP_REDUCE: e = launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream); break;
+    case P_STEP:
+        if constexpr (narrow)
+            e = sr ? launch_step_b<S, M_STORE | M_SR>(p, block, c->stream) : launch_step_b<S, M_STORE>(p, block, c->stream);
+        else
+            e = launch_step_b<S, M_STORE>(p, block, c->stream);
+        break;
+    case P_STEP_REDUCE:
+        if constexpr (narrow)
+            e = sr ? launch_step_b<S, M_STORE | M_REDUCE | M_SR>(p, block, c->stream)
+                   : launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream);
+        else
+            e = launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream);
+        break;
     case P_FIELDS_REDUCE: e = launch_step_t<S, 256, M_FIELDS | M_REDUCE>(p, c->stream); break;
     case P_TABLES: e = launch_step_t<S, 256, M_TABLES>(p, c->stream); break;
     }

@@ -152,9 +152,22 @@ hipError_t launch_batch_t(lbm_batch *b, int flip)
 {
     using C = typename Traits<S>::C;
     const int per_xcd = (b->n_items + 7) / 8;
-    hipLaunchKernelGGL((k_step_batch<S, BLOCK, M_STORE>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream,
-                       (const KParams<C> *)b->d_params, b->nruns, b->n_items, per_xcd, flip,
-                       (const unsigned *)b->d_tick);
+    const bool sr = (S == ST_F16 || S == ST_BF16) && (b->runs[0].flags & LBM_ROUND_STOCHASTIC);
+    if constexpr (S == ST_F16 || S == ST_BF16) {
+        if (sr)
+            hipLaunchKernelGGL((k_step_batch<S, BLOCK, M_STORE | M_SR>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream,
+                               (const KParams<C> *)b->d_params, b->nruns, b->n_items, per_xcd, flip,
+                               (const unsigned *)b->d_tick);
+        else
+            hipLaunchKernelGGL((k_step_batch<S, BLOCK, M_STORE>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream,
+                               (const KParams<C> *)b->d_params, b->nruns, b->n_items, per_xcd, flip,
+                               (const unsigned *)b->d_tick);
+    } else {
+        (void)sr;
+        hipLaunchKernelGGL((k_step_batch<S, BLOCK, M_STORE>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream,
+                           (const KParams<C> *)b->d_params, b->nruns, b->n_items, per_xcd, flip,
+                           (const unsigned *)b->d_tick);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, b->stream, b->d_tick);
@@ -279,6 +292,11 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
         if (d.nx < 5 || d.ny < 5 || !d.solid || !d.rho1 || !d.rho2 || (d.flags & ~(unsigned)FL_ALL) || !(d.tau > 0.5) ||
             !std::isfinite(d.tau) || !std::isfinite(d.G_c) || !std::isfinite(d.G_ads) ||
             (d.wall_kind != LBM_WALL_FLAT && d.wall_kind != LBM_WALL_CYLINDER)) {
+            delete b;
+            return LBM_EINVAL;
+        }
+        // stochastic rounding is a property of the launch: all runs or none
+        if (r > 0 && (d.flags & LBM_ROUND_STOCHASTIC) != (runs[0].flags & LBM_ROUND_STOCHASTIC)) {
             delete b;
             return LBM_EINVAL;
         }

@@ -34,7 +34,8 @@ enum : int {
     M_STORE = 1,   // collide and write the post-collision set
     M_REDUCE = 2,  // per-workgroup diagnostic partial sums
     M_FIELDS = 4,  // write rho_1, rho_2, u (FP64)
-    M_TABLES = 8   // write link bits and resolved stencil sources
+    M_TABLES = 8,  // write link bits and resolved stencil sources
+    M_SR = 16      // stochastic rounding of FP16 / BF16 stores (compile-time)
 };
 
 // ---------------------------------------------------------------------------

@@ -390,8 +390,8 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
             c1[k] = (C)3 * wr;
             c2[k] = (C)4.5 * wr;
         }
-        const bool sr = (S == ST_F16 || S == ST_BF16) && (p.flags & FL_ROUND_STOCHASTIC);
-        uint32_t rs = sr ? sr_seed(node, p.tick) : 0u;
+        constexpr bool sr = (S == ST_F16 || S == ST_BF16) && (MODE & M_SR);
+        uint32_t rs = sr ? sr_seed(node, p.tick) : 1u;
         const uint32_t voff = (uint32_t)node * (uint32_t)sizeof(R);
         C gs[2][9];
 #pragma unroll
@@ -414,22 +414,29 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
                 gs[k][o] = p.omw * f[k][o] + w * (E - O);
             }
         }
-        // stores in direction order; with stochastic rounding one random
-        // word per direction, low half for component 1, high for component 2
+        // encode (with stochastic rounding: one random word per direction,
+        // low half for component 1, high half for component 2), then store;
+        // the rounding mode is a compile-time mode bit, so each kernel
+        // carries only its own encoder
+        R out[2][9];
+        if constexpr (sr) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const uint32_t rw = xorshift32(rs);
+                out[0][i] = T::enc_sr(gs[0][i], rw);
+                out[1][i] = T::enc_sr(gs[1][i], rw >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                out[0][i] = T::enc(gs[0][i]);
+                out[1][i] = T::enc(gs[1][i]);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const uint32_t rw = sr ? xorshift32(rs) : 0u;
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                R out;
-                if (S == ST_F16 || S == ST_BF16) {
-                    if (sr) out = T::enc_sr(gs[k][i], k == 0 ? rw : rw >> 16);
-                    else out = T::enc(gs[k][i]);
-                } else {
-                    out = T::enc(gs[k][i]);
-                }
-                pop_store<S>(mw, k, i, voff, out);
-            }
+            pop_store<S>(mw, 0, i, voff, out[0][i]);
+            pop_store<S>(mw, 1, i, voff, out[1][i]);
         }
     }
 }
