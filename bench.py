@@ -232,6 +232,36 @@ def porous_precision(args):
     print(json.dumps(out), flush=True)
 
 
+def cylinder_sweep(args):
+    """The droplet-on-cylinder sweep (400x400, seven adhesion values, 20000
+    steps) in every storage, against the FP64 oracle angles stored in
+    tests/golden/cylinder_theta.json (written from the oracle alone)."""
+    with open(os.path.join(ROOT, "tests", "golden", "cylinder_theta.json")) as f:
+        ref = json.load(f)
+    cases = [("f64", lbm.F64, 0), ("f32", lbm.F32, 0), ("f16", lbm.F16, 0),
+             ("f16_sr", lbm.F16, lbm.ROUND_STOCHASTIC), ("bf16", lbm.BF16, 0),
+             ("bf16_sr", lbm.BF16, lbm.ROUND_STOCHASTIC)]
+    rows = []
+    for c in ref["cases"]:
+        wl = W.cylinder_drop(G_ads=c["G_ads"])
+        row = {"G_ads": c["G_ads"], "theta_oracle": round(c["theta_deg"], 4)}
+        for name, st, fl in cases:
+            g = lbm.lattice_from_workload(wl, st, fl)
+            g.step(ref["steps"])
+            try:
+                row[name] = round(abs(g.contact_angle(wl.wall_kind, wl.wall) - c["theta_deg"]), 4)
+            except lbm.LbmError:
+                row[name] = None
+            g.close()
+        rows.append(row)
+        print(f"[cylinder] {row}", file=sys.stderr, flush=True)
+    worst = {name: max(r[name] for r in rows if r[name] is not None) for name, _, _ in cases}
+    print(json.dumps({"metric": "cylinder sweep: |theta - theta_oracle| (deg) per storage",
+                      "workload": f"droplet on a cylinder, 400x400, {ref['steps']} steps, G_ads in "
+                                  f"{[r['G_ads'] for r in rows]}",
+                      "worst_abs_err_deg": worst, "cases": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,9 +273,10 @@ def main():
     ap.add_argument("--tile", default="auto", help="auto or BLOCK,ROWS[,SCHED]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--workload", default="constrictions", choices=["constrictions", "calibration", "porous"],
+    ap.add_argument("--workload", default="constrictions",
+                    choices=["constrictions", "calibration", "porous", "cylinder"],
                     help="constrictions: the 16384x2048 channel (default); calibration: the 512-run batch; "
-                         "porous: the storage precision study")
+                         "porous: the storage precision study; cylinder: the contact-angle sweep per storage")
     ap.add_argument("--record-every", type=int, default=1000, help="porous: recording interval")
     ap.add_argument("--full", action="store_true", help="calibration: run the configured 10000 steps and "
                     "report contact angles")
@@ -276,6 +307,9 @@ def main():
         return
     if args.workload == "porous":
         porous_precision(args)
+        return
+    if args.workload == "cylinder":
+        cylinder_sweep(args)
         return
 
     import torch  # device streams and events only
