@@ -262,6 +262,44 @@ def cylinder_sweep(args):
                       "worst_abs_err_deg": worst, "cases": rows}), flush=True)
 
 
+def scheme_comparison(args):
+    """Original (constant G_w1) against improved (local G(x), Eq. 11)
+    adhesion on the droplet-on-cylinder case, swept over lambda = G_w1 /
+    G_w2 with G_w2 = G_c: contact angle, largest velocity (the spurious
+    currents of Sec. 3.2), smallest and largest rho_1, and the mean rho_1
+    on the wall under the cylinder, far from the droplet (the mass-transfer
+    layer: the dissolved level there is 0.098 without one)."""
+    lams = [0.26, 0.35, 0.47, 0.6, 0.88, 1.0, 1.2, 1.35, 1.6]
+    steps = args.steps if args.steps_given else 20000
+    storage = STORAGES[args.storage]
+    wl = W.cylinder_drop()
+    cx, cy, Rs = wl.wall
+    y, x = np.mgrid[0:wl.ny, 0:wl.nx]
+    dist = np.hypot(x - cx, y - cy) - (Rs - 0.5)
+    band = (wl.solid == 0) & (dist < 1.5) & (y < cy - 0.5 * (Rs - 0.5))
+    rows = []
+    for scheme, fl in (("original", lbm.SCHEME_ORIGINAL), ("improved", 0)):
+        for lam in lams:
+            g = lbm.lattice_from_workload(wl, storage, fl)
+            g.set_adhesion(lam * wl.G_c, wl.G_c, 0.8)
+            g.step(steps)
+            m = g.reduce()
+            try:
+                th = round(g.contact_angle(wl.wall_kind, wl.wall), 3)
+            except lbm.LbmError:
+                th = None
+            r1 = g.get_fields()[0]
+            row = {"scheme": scheme, "lambda": lam, "theta_deg": th, "max_u": float(m[4]),
+                   "min_rho1": float(m[5]), "max_rho1": float(m[6]),
+                   "wall_rho1_below": round(float(r1[band].mean()), 5), "nonfinite": int(m[7])}
+            rows.append(row)
+            g.close()
+            print(f"[schemes] {row}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "original vs improved adhesion: angle, spurious currents, density extremes, "
+                                "wall layer", "workload": f"droplet on a cylinder 400x400, {steps} steps, "
+                                f"{args.storage} storage, G_w2 = G_c = 0.9, delta = 0.8", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,9 +312,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--workload", default="constrictions",
-                    choices=["constrictions", "calibration", "porous", "cylinder"],
+                    choices=["constrictions", "calibration", "porous", "cylinder", "schemes"],
                     help="constrictions: the 16384x2048 channel (default); calibration: the 512-run batch; "
-                         "porous: the storage precision study; cylinder: the contact-angle sweep per storage")
+                         "porous: the storage precision study; cylinder: the contact-angle sweep per storage; "
+                         "schemes: original against improved adhesion")
     ap.add_argument("--record-every", type=int, default=1000, help="porous: recording interval")
     ap.add_argument("--full", action="store_true", help="calibration: run the configured 10000 steps and "
                     "report contact angles")
@@ -310,6 +349,9 @@ def main():
         return
     if args.workload == "cylinder":
         cylinder_sweep(args)
+        return
+    if args.workload == "schemes":
+        scheme_comparison(args)
         return
 
     import torch  # device streams and events only
