@@ -584,13 +584,8 @@ __device__ __forceinline__ void process_unit(const KParams<typename Traits<S>::C
 // Grid: 8 * per_xcd workgroups over the run's n_units units;
 // workgroup b takes unit (b % 8) * per_xcd + b / 8, so each XCD works on a
 // contiguous part of the lattice.
-#ifdef LBM_WAVES_PER_EU
-#define LBM_STEP_ATTR __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
-#else
-#define LBM_STEP_ATTR
-#endif
 template <int S, int BLOCK, int MODE>
-__global__ void __launch_bounds__(BLOCK) LBM_STEP_ATTR k_step(const KParams<typename Traits<S>::C> p, int per_xcd)
+__global__ void __launch_bounds__(BLOCK) k_step(const KParams<typename Traits<S>::C> p, int per_xcd)
 {
     using C = typename Traits<S>::C;
     __shared__ PsiPair<C> ring[8][BLOCK];
