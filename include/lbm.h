@@ -86,7 +86,7 @@ enum {
 };
 
 /* Tile schedule bits for lbm_set_tile. */
-enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2, LBM_SCHED_XCD_SLABS = 4 };
+enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2, LBM_SCHED_XCD_SLABS = 4, LBM_SCHED_TWO_STEP = 8 };
 
 /* Contact-angle wall kinds for lbm_contact_angle. */
 enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
@@ -190,15 +190,22 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * width block - 4 columns) and rows per workgroup segment.  seg_rows = 0
  * is persistent scheduling: one work unit per resident workgroup, each
  * taking an equal share of the strip rows.  Default after lbm_create:
- * block 256, seg_rows 16, sched LBM_SCHED_ALIGN | LBM_SCHED_BANDS (FP16 /
- * BF16: LBM_SCHED_BANDS).  Results do not
+ * FP32 block 128, seg_rows 64, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; FP16 /
+ * BF16 block 256, seg_rows 16, LBM_SCHED_BANDS; FP64 block 256, seg_rows
+ * 16, LBM_SCHED_ALIGN | LBM_SCHED_BANDS.  Results do not
  * depend on the tile shape (bitwise).  sched bits: LBM_SCHED_ALIGN makes
  * strips a multiple of 128 bytes wide from x = 0, so that stores never
  * cover part of a cache line shared with another workgroup;
  * LBM_SCHED_BANDS (fixed segments only) runs units across the strips
  * first, so concurrent workgroups cover whole rows; LBM_SCHED_XCD_SLABS
  * gives each of the 8 XCDs one contiguous slab of rows, one workgroup per
- * strip marching down it (seg_rows is ignored).  lbm_autotune times the
+ * strip marching down it (seg_rows is ignored).  LBM_SCHED_TWO_STEP (FP32,
+ * FP16, BF16) fuses two time steps per launch: the first step's
+ * post-collision rows stay in LDS and the second step pulls them from
+ * there, so HBM is read and written once per two steps (strips lose 5
+ * columns of halo on each side instead of 2); steps that record
+ * diagnostics and an odd last step run alone.  Results are bitwise those
+ * of single steps.  lbm_autotune times the
  * current tile and then every candidate for `steps` steps each on the
  * current state (restoring state and time afterwards); a candidate replaces
  * the best so far only when it is at least 2 % faster, so timing noise does

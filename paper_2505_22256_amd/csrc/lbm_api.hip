@@ -96,7 +96,7 @@ int ensure_partials(lbm_ctx *c, size_t nparts)
 }
 
 template <class C>
-KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int seg_rows)
+KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int seg_rows, int halo = 2)
 {
     KParams<C> p;
     std::memset(&p, 0, sizeof p);
@@ -106,7 +106,7 @@ KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int 
     p.ny = c->ny;
     p.flags = c->flags;
     tile_counts(block, seg_rows, c->nx, c->ny, &p.n_strips, &p.n_segs, c->sched,
-                (int)(128 / elem_size(c->storage)), &p.strip_w);
+                (int)(128 / elem_size(c->storage)), &p.strip_w, halo);
     p.band_order = (c->sched & SCHED_BANDS) ? 1 : 0;
     p.xcd_slabs = 0;
     p.n_units = p.n_strips * p.n_segs;
@@ -160,8 +160,26 @@ int resident_capacity(lbm_ctx *c, int block)
     return per_cu * c->cus;
 }
 
-// Kinds of pass over the lattice.
-enum Pass { P_STEP, P_STEP_REDUCE, P_FIELDS_REDUCE, P_TABLES };
+// Kinds of pass over the lattice.  P_STEP2 advances two steps.
+enum Pass { P_STEP, P_STEP_REDUCE, P_FIELDS_REDUCE, P_TABLES, P_STEP2 };
+
+template <int S, int BLOCK, int MODE>
+hipError_t launch_step2_t(const KParams<typename Traits<S>::C> &p, hipStream_t st)
+{
+    const int per_xcd = (p.n_units + 7) / 8;
+    hipLaunchKernelGGL((k_step2<S, BLOCK, MODE>), dim3(per_xcd * 8), dim3(BLOCK), 0, st, p, per_xcd);
+    return hipGetLastError();
+}
+
+template <int S, int MODE>
+hipError_t launch_step2_b(const KParams<typename Traits<S>::C> &p, int block, hipStream_t st)
+{
+    switch (block) {
+    case 64: return launch_step2_t<S, 64, MODE>(p, st);
+    case 128: return launch_step2_t<S, 128, MODE>(p, st);
+    default: return launch_step2_t<S, 256, MODE>(p, st);
+    }
+}
 
 // Launch one pass reading buf[cur].  P_STEP* write buf[cur^1] (the caller
 // flips cur).  Returns the number of partial records in *nparts.
@@ -169,17 +187,18 @@ template <int S>
 int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts)
 {
     using C = typename Traits<S>::C;
-    const int block = (pass == P_STEP || pass == P_STEP_REDUCE) ? c->block : 256;
+    const bool stepping = pass == P_STEP || pass == P_STEP_REDUCE || pass == P_STEP2;
+    const int block = stepping ? c->block : 256;
     const int seg = c->seg_rows > 0 ? c->seg_rows : 64;
-    KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, seg);
-    if ((c->sched & SCHED_XCD_SLABS) && (pass == P_STEP || pass == P_STEP_REDUCE)) {
+    KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, seg, pass == P_STEP2 ? 5 : 2);
+    if ((c->sched & SCHED_XCD_SLABS) && stepping) {
         // one unit per (strip, row slab); the grid is 8 * strips so that
         // workgroup b lands on XCD b % 8 = its slab
         p.xcd_slabs = 1;
         p.band_order = 0;
         p.n_segs = 8;
         p.n_units = 8 * p.n_strips;
-    } else if (c->seg_rows == 0 && (pass == P_STEP || pass == P_STEP_REDUCE)) {
+    } else if (c->seg_rows == 0 && stepping) {
         // persistent: one unit per resident workgroup, balanced rows per unit
         const int cap = resident_capacity<S>(c, block);
         const long long rows = (long long)p.n_strips * c->ny;
@@ -217,6 +236,15 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
                    : launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream);
         else
             e = launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream);
+        break;
+    case P_STEP2:
+        if constexpr (S == ST_F64) {
+            e = hipErrorInvalidValue;  // refused by lbm_set_tile
+        } else if constexpr (narrow) {
+            e = sr ? launch_step2_b<S, M_STORE | M_SR>(p, block, c->stream) : launch_step2_b<S, M_STORE>(p, block, c->stream);
+        } else {
+            e = launch_step2_b<S, M_STORE>(p, block, c->stream);
+        }
         break;
     case P_FIELDS_REDUCE: e = launch_step_t<S, 256, M_FIELDS | M_REDUCE>(p, c->stream); break;
     case P_TABLES: e = launch_step_t<S, 256, M_TABLES>(p, c->stream); break;
@@ -356,11 +384,20 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
         return LBM_ENOMEM;
     }
     c->solid.assign((size_t)c->N, 0);
-    // measured defaults on the 16384 x 2048 channel: 16-row segments in row
-    // bands; 128-byte aligned strips pay off for 4- and 8-byte storage only
-    c->block = 256;
-    c->seg_rows = 16;
-    c->sched = (storage == LBM_F16 || storage == LBM_BF16) ? SCHED_BANDS : (SCHED_ALIGN | SCHED_BANDS);
+    // measured defaults on the 16384 x 2048 channel: FP32 fuses two steps
+    // per launch (128-thread strips, 64-row segments in row bands); FP16 /
+    // BF16 (issue-bound, no gain from fusing) and FP64 run one step per
+    // launch in 16-row segments and row bands, FP64 with 128-byte aligned
+    // strips
+    if (storage == LBM_F32) {
+        c->block = 128;
+        c->seg_rows = 64;
+        c->sched = SCHED_TWO_STEP | SCHED_BANDS;
+    } else {
+        c->block = 256;
+        c->seg_rows = 16;
+        c->sched = storage == LBM_F64 ? (SCHED_ALIGN | SCHED_BANDS) : SCHED_BANDS;
+    }
     *out = c;
     return LBM_OK;
 }
@@ -546,8 +583,20 @@ int lbm_step(lbm_ctx *c, int n)
     int rc = ready(c);
     if (rc) return rc;
     if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
+    const bool two = (c->sched & SCHED_TWO_STEP) && c->storage != LBM_F64;
     for (int s = 0; s < n; ++s) {
-        if (c->diag_every > 0 && c->t % c->diag_every == 0) {
+        const bool diag_now = c->diag_every > 0 && c->t % c->diag_every == 0;
+        const bool diag_next = c->diag_every > 0 && (c->t + 1) % c->diag_every == 0;
+        if (two && !diag_now && !diag_next && n - s >= 2) {
+            // two fused steps; a step that records diagnostics runs alone
+            rc = run_pass(c, P_STEP2, nullptr, nullptr, nullptr, nullptr, nullptr);
+            if (rc) return rc;
+            c->cur ^= 1;
+            c->t += 2;
+            ++s;
+            continue;
+        }
+        if (diag_now) {
             int nparts = 0;
             rc = run_pass(c, P_STEP_REDUCE, nullptr, nullptr, nullptr, nullptr, &nparts);
             if (rc) return rc;
@@ -706,8 +755,10 @@ int lbm_get_tables(lbm_ctx *c, uint8_t *link, int32_t *nw_list, int32_t *nw_src,
 int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
 {
     if (!c) return LBM_EINVAL;
-    if (!valid_block(block) || seg_rows < 0 || (sched & ~7u))
-        return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..7");
+    if (!valid_block(block) || seg_rows < 0 || (sched & ~15u))
+        return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..15");
+    if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64)
+        return set_err(c, LBM_EINVAL, "two fused steps need FP32, FP16 or BF16 storage");
     c->block = block;
     c->seg_rows = seg_rows;
     c->sched = sched;
@@ -744,16 +795,20 @@ int lbm_autotune(lbm_ctx *c, int steps)
     int best_b = cur_b, best_r = cur_r;
     unsigned best_s = cur_s;
     float best_ms = 1e30f;
-    // candidate -1 is the incumbent tile; the rest need a 2 % margin to win
-    for (int cand = -1; cand < 3 * 8 * 6 && e == hipSuccess && rc == LBM_OK; ++cand) {
+    // candidate -1 is the incumbent tile; the rest need a 2 % margin to win.
+    // Each block x rows x schedule is tried with one step per launch and,
+    // except in FP64, with two fused steps per launch.
+    const int n_two = c->storage == LBM_F64 ? 1 : 2;
+    for (int cand = -1; cand < 3 * 8 * 6 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
         int cb = cur_b, cr = cur_r;
         unsigned sc = cur_s;
         if (cand >= 0) {
-            const int bi = cand / 48, ri = (cand / 6) % 8;
+            const int tw = cand / 144, bi = (cand / 48) % 3, ri = (cand / 6) % 8;
             sc = (unsigned)(cand % 6);  // 0-3: align/bands bits; 4, 5: XCD slabs (+ align)
             if (rows[ri] > c->ny && ri > 1) continue;
             if (rows[ri] == 0 && (sc & SCHED_BANDS)) continue;  // bands need fixed segments
             if ((sc & SCHED_XCD_SLABS) && ri != 0) continue;   // slabs ignore seg_rows
+            if (tw) sc |= SCHED_TWO_STEP;
             cb = blocks[bi];
             cr = rows[ri];
         }

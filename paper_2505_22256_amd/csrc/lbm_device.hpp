@@ -35,7 +35,9 @@ enum : int {
     M_REDUCE = 2,  // per-workgroup diagnostic partial sums
     M_FIELDS = 4,  // write rho_1, rho_2, u (FP64)
     M_TABLES = 8,  // write link bits and resolved stencil sources
-    M_SR = 16      // stochastic rounding of FP16 / BF16 stores (compile-time)
+    M_SR = 16,     // stochastic rounding of FP16 / BF16 stores (compile-time)
+    M_LDS = 32,    // first of two fused steps: post-collision values to the LDS ring
+    M_TWO = 64     // kernel advances two steps per launch
 };
 
 // ---------------------------------------------------------------------------

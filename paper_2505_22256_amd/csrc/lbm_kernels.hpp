@@ -64,19 +64,30 @@ __device__ __forceinline__ void issue_node(const PopMem<S> &m, int nx, const Axi
     }
 }
 
+// Where the bounce-back path reads f*_opp(i)(x, t-1) of the node itself:
+// the post-collision set in HBM (one step per launch) or the LDS ring of
+// the first of two fused steps.
+template <int S> struct GlobalReload {
+    const PopMem<S> &m;
+    uint32_t off;  // byte offset of the node
+    __device__ __forceinline__ typename Traits<S>::raw_t operator()(int k, int i) const
+    {
+        return pop_load<S>(m, k, i, off);
+    }
+};
+
 // Turn the pulled values of one node into its state: deviations g_i of
 // f_i(x, t), with halfway bounce-back f_i(x, t) = f*_opp(i)(x, t-1) where
 // the source is unavailable (a sentinel or outside the domain), and the
 // densities rho_k = sum_i f_i (Eq. 3) in the definition's summation order.
-template <int S>
-__device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
-                                             const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
-                                             RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
-                                             typename Traits<S>::C &r2)
+template <int S, class Reload>
+__device__ __forceinline__ void process_node_src(const KParams<typename Traits<S>::C> &p, const Reload &reload,
+                                                 const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
+                                                 RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
+                                                 typename Traits<S>::C &r2)
 {
     using T = Traits<S>;
     using C = typename T::C;
-    using R = typename T::raw_t;
     st.info = 256;
     if (!valid) return;
     // the node's own rest slot is always inside the domain
@@ -98,7 +109,6 @@ __device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C
     st.info = 0;
     if (__builtin_isnan(s1 + s2)) {
         // an unavailable source (or a non-finite state): reflect
-        const uint32_t node = (uint32_t)(ry.c * p.nx + cx.c);
         int info = 0;
         s1 = 0;
         s2 = 0;
@@ -109,8 +119,8 @@ __device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C
             pull_source(i, cx, ry, col, row, ok);
             if (i > 0 && (!ok || T::sent(q.v[0][i]))) {
                 info |= 1 << (i - 1);
-                st.f[0][i] = T::dec(pop_load<S>(m, 0, opp(i), node * (uint32_t)sizeof(R)));
-                st.f[1][i] = T::dec(pop_load<S>(m, 1, opp(i), node * (uint32_t)sizeof(R)));
+                st.f[0][i] = T::dec(reload(0, opp(i)));
+                st.f[1][i] = T::dec(reload(1, opp(i)));
             }
             s1 += st.f[0][i];
             s2 += st.f[1][i];
@@ -121,6 +131,16 @@ __device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C
     }
     r1 = s1;
     r2 = s2;
+}
+
+template <int S>
+__device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
+                                             const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
+                                             RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
+                                             typename Traits<S>::C &r2)
+{
+    const GlobalReload<S> reload{m, (uint32_t)(ry.c * p.nx + cx.c) * (uint32_t)sizeof(typename Traits<S>::raw_t)};
+    process_node_src<S>(p, reload, cx, ry, valid, q, st, r1, r2);
 }
 
 // Process a prefetched row: node state into `st`, psi into the LDS ring.
@@ -234,16 +254,27 @@ __device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int ti
 // collision and the selected outputs.
 template <int S, int BLOCK, int MODE>
 __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mw,
-                                            const Axis &cx, int y, const RowState<typename Traits<S>::C> &st,
-                                            PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
+                                            const Axis &cx, int y, int yw,
+                                            const RowState<typename Traits<S>::C> &st,
+                                            PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc,
+                                            typename Traits<S>::raw_t (*fring)[2][9][BLOCK] = nullptr,
+                                            unsigned dtick = 0)
 {
     using T = Traits<S>;
     using C = typename T::C;
     using R = typename T::raw_t;
-    const int node = y * p.nx + cx.c;
+    // y numbers the LDS ring rows (it may lie outside the lattice in a halo
+    // of the fused two-step kernel); yw is the lattice row after wrapping
+    const int node = yw * p.nx + cx.c;
     const int tid = threadIdx.x;
 
-    if (st.info & 256) {  // solid node
+    if (st.info & 256) {  // solid node (or outside the domain)
+        if (MODE & M_LDS) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) fring[y & 3][k][i][tid] = T::sentinel();
+        }
         if (MODE & M_FIELDS) {
             p.out_rho1[node] = 0.0;
             p.out_rho2[node] = 0.0;
@@ -391,7 +422,7 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
             c2[k] = (C)4.5 * wr;
         }
         constexpr bool sr = (S == ST_F16 || S == ST_BF16) && (MODE & M_SR);
-        uint32_t rs = sr ? sr_seed(node, p.tick) : 1u;
+        uint32_t rs = sr ? sr_seed(node, p.tick + dtick) : 1u;
         const uint32_t voff = (uint32_t)node * (uint32_t)sizeof(R);
         C gs[2][9];
 #pragma unroll
@@ -433,10 +464,18 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
                 out[1][i] = T::enc(gs[1][i]);
             }
         }
+        if constexpr (MODE & M_LDS) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            pop_store<S>(mw, 0, i, voff, out[0][i]);
-            pop_store<S>(mw, 1, i, voff, out[1][i]);
+            for (int i = 0; i < 9; ++i) {
+                fring[y & 3][0][i][tid] = out[0][i];
+                fring[y & 3][1][i][tid] = out[1][i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                pop_store<S>(mw, 0, i, voff, out[0][i]);
+                pop_store<S>(mw, 1, i, voff, out[1][i]);
+            }
         }
     }
 }
@@ -520,19 +559,19 @@ __device__ __forceinline__ void process_segment(const KParams<typename Traits<S>
         process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rc);
         if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
-        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, ra, ring, acc);
+        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, y, ra, ring, acc);
         ++y;
         if (y >= y1) break;
         process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, ra);
         if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
-        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, rb, ring, acc);
+        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, y, rb, ring, acc);
         ++y;
         if (y >= y1) break;
         process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rb);
         if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
-        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, rc, ring, acc);
+        if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, y, rc, ring, acc);
         ++y;
     }
 }
@@ -543,41 +582,185 @@ __device__ __forceinline__ void process_segment(const KParams<typename Traits<S>
 // band_order the units of a fixed-segment tiling are taken across the
 // strips first, so that workgroups running at the same time cover whole
 // rows of the lattice.
+template <class Seg>
+__device__ __forceinline__ void for_unit_segments(int n_strips, int n_segs, int ny, int xcd_slabs, int band_order,
+                                                  int u, int n_units, Seg &&seg)
+{
+    if (xcd_slabs) {
+        // workgroup b runs on XCD b % 8: slab b % 8 of the rows, strip b / 8
+        const int strip = u >> 3, slab = u & 7;
+        const int y0 = (int)(((long long)slab * ny) >> 3);
+        const int y1 = (int)(((long long)(slab + 1) * ny) >> 3);
+        if (strip < n_strips && y1 > y0) seg(strip, y0, y1);
+        return;
+    }
+    if (band_order && n_units == n_strips * n_segs) {
+        const int strip = u % n_strips, sg = u / n_strips;
+        const int y0 = (int)(((long long)sg * ny) / n_segs);
+        const int y1 = (int)(((long long)(sg + 1) * ny) / n_segs);
+        seg(strip, y0, y1);
+        return;
+    }
+    const long long R = (long long)n_strips * ny;
+    long long q0 = (long long)u * R / n_units;
+    const long long q1 = (long long)(u + 1) * R / n_units;
+    bool first = true;
+    while (q0 < q1) {
+        const int strip = (int)(q0 / ny);
+        const int y0 = (int)(q0 - (long long)strip * ny);
+        const long long end = (long long)(strip + 1) * ny < q1 ? (long long)(strip + 1) * ny : q1;
+        const int y1 = (int)(end - (long long)strip * ny);
+        if (!first) __syncthreads();  // the LDS rings are reused
+        seg(strip, y0, y1);
+        first = false;
+        q0 = end;
+    }
+}
+
 template <int S, int BLOCK, int MODE>
 __device__ __forceinline__ void process_unit(const KParams<typename Traits<S>::C> &p, int u, int n_units,
                                              PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc)
 {
     const PopMem<S> mr = make_mem<S>(p.A, p.N);
     const PopMem<S> mw = make_mem<S>(p.B, p.N);
-    if (p.xcd_slabs) {
-        // workgroup b runs on XCD b % 8: slab b % 8 of the rows, strip b / 8
-        const int strip = u >> 3, slab = u & 7;
-        const int y0 = (int)(((long long)slab * p.ny) >> 3);
-        const int y1 = (int)(((long long)(slab + 1) * p.ny) >> 3);
-        if (strip < p.n_strips && y1 > y0) process_segment<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring, acc);
-        return;
+    for_unit_segments(p.n_strips, p.n_segs, p.ny, p.xcd_slabs, p.band_order, u, n_units,
+                      [&](int strip, int y0, int y1) {
+                          process_segment<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring, acc);
+                      });
+}
+
+// ---------------------------------------------------------------------------
+// Two fused time steps per launch (temporal blocking).  The first step runs
+// exactly the code of the single step but keeps its post-collision rows in
+// an LDS ring instead of HBM; the second step pulls from that ring, five
+// rows behind, and writes HBM.  HBM then sees one read and one write of the
+// populations per two steps (plus a wider halo: 5 columns and 5 rows on
+// each side instead of 2), and the result is bitwise that of two single
+// steps.
+// ---------------------------------------------------------------------------
+template <int S, int BLOCK>
+using FRing = typename Traits<S>::raw_t (*)[2][9][BLOCK];
+
+// Pull f(x, t+1) = f*(x - e_i, t) of row r from the ring (lane = column).
+template <int S, int BLOCK>
+__device__ __forceinline__ void issue_row_lds(FRing<S, BLOCK> fring, int r, RawRow<S> &q)
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int src = tid - qx(i);
+        const bool in = src >= 0 && src < BLOCK;
+        const int lane = in ? src : tid;
+        const int slot = (r - qy(i)) & 3;
+        q.v[0][i] = in ? fring[slot][0][i][lane] : Traits<S>::sentinel();
+        q.v[1][i] = in ? fring[slot][1][i][lane] : Traits<S>::sentinel();
     }
-    if (p.band_order && n_units == p.n_strips * p.n_segs) {
-        const int strip = u % p.n_strips, seg = u / p.n_strips;
-        const int y0 = (int)(((long long)seg * p.ny) / p.n_segs);
-        const int y1 = (int)(((long long)(seg + 1) * p.ny) / p.n_segs);
-        process_segment<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring, acc);
-        return;
+}
+
+template <int S, int BLOCK> struct LdsReload {
+    FRing<S, BLOCK> fring;
+    int slot, lane;
+    __device__ __forceinline__ typename Traits<S>::raw_t operator()(int k, int i) const
+    {
+        return fring[slot][k][i][lane];
     }
-    const long long R = (long long)p.n_strips * p.ny;
-    long long q0 = (long long)u * R / n_units;
-    const long long q1 = (long long)(u + 1) * R / n_units;
-    bool first = true;
-    while (q0 < q1) {
-        const int strip = (int)(q0 / p.ny);
-        const int y0 = (int)(q0 - (long long)strip * p.ny);
-        const long long end = (long long)(strip + 1) * p.ny < q1 ? (long long)(strip + 1) * p.ny : q1;
-        const int y1 = (int)(end - (long long)strip * p.ny);
-        if (!first) __syncthreads();  // the ring is reused
-        process_segment<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring, acc);
-        first = false;
-        q0 = end;
+};
+
+template <int S, int BLOCK>
+__device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>::C> &p, FRing<S, BLOCK> fring,
+                                                const Axis &cx, bool col_ok, int r,
+                                                PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
+                                                RowState<typename Traits<S>::C> &st)
+{
+    using C = typename Traits<S>::C;
+    const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
+    RawRow<S> q;
+    issue_row_lds<S, BLOCK>(fring, r, q);
+    const LdsReload<S, BLOCK> reload{fring, r & 3, (int)threadIdx.x};
+    C r1 = 0, r2 = 0;
+    process_node_src<S>(p, reload, cx, ry, col_ok && ry.ok, q, st, r1, r2);
+    PsiPair<C> ps;
+    ps.a = (st.info & 256) ? lds_sentinel<C>() : r1;
+    ps.b = (st.info & 256) ? lds_sentinel<C>() : r2;
+    ring[ring_slot(r)][threadIdx.x] = ps;
+}
+
+// Rows [y0, y1) of a strip, two steps.  Iteration p: step 1 processes row p
+// (pulled from HBM), step 2 processes row p - 5 (pulled from the ring), the
+// loads of row p + 1 are issued, one barrier, then step 1 finishes row p - 2
+// into the ring and step 2 finishes row p - 7 into HBM.  Lanes cover columns
+// x0-5 .. x1+4: step 1 needs psi(t) there, finishes x0-3 .. x1+2; step 2
+// needs psi(t+1) on x0-2 .. x1+1 and finishes x0 .. x1-1.
+template <int S, int BLOCK, int MODE>
+__device__ __forceinline__ void process_segment2(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mr,
+                                                 const PopMem<S> &mw, int strip, int y0, int y1,
+                                                 PsiPair<typename Traits<S>::C> (*ring1)[BLOCK],
+                                                 PsiPair<typename Traits<S>::C> (*ring2)[BLOCK],
+                                                 FRing<S, BLOCK> fring, RedAcc &acc)
+{
+    using C = typename Traits<S>::C;
+    constexpr int M1 = (MODE & M_SR) | M_STORE | M_LDS;
+    constexpr int M2 = (MODE & M_SR) | M_STORE;
+    const int tid = threadIdx.x;
+    int x0, x1;
+    if (p.strip_w > 0) {
+        x0 = strip * p.strip_w;
+        x1 = x0 + p.strip_w < p.nx ? x0 + p.strip_w : p.nx;
+    } else {
+        x0 = (int)(((long long)strip * p.nx) / p.n_strips);
+        x1 = (int)(((long long)(strip + 1) * p.nx) / p.n_strips);
     }
+    const int w = x1 - x0;
+    const Axis cx = make_axis(x0 - 5 + tid, p.nx, p.flags & FL_PERIODIC_X);
+    const bool act1 = tid < w + 10 && cx.ok;
+    const bool in1 = tid >= 2 && tid < w + 8;
+    const bool act2 = tid >= 3 && tid < w + 7 && cx.ok;
+    const bool in2 = tid >= 5 && tid < w + 5;
+    const int p_first = y0 - 5, p_pull_last = y1 + 4, p_last = y1 + 6;
+    const bool wrap_y = p.flags & FL_PERIODIC_Y;
+
+    RowState<C> a1, b1, c1, a2, b2, c2;
+    RawRow<S> q;
+    issue_row<S>(p, mr, cx, act1, p_first, q);
+    auto iter = [&](int pp, RowState<C> &s1w, RowState<C> &s1f, RowState<C> &s2w, RowState<C> &s2f) {
+        if (pp <= p_pull_last) process_row<S, BLOCK>(p, mr, cx, act1, pp, q, ring1, s1w);
+        if (pp - 5 >= y0 - 2 && pp - 5 <= y1 + 1) process_row_lds<S, BLOCK>(p, fring, cx, act2, pp - 5, ring2, s2w);
+        if (pp + 1 <= p_pull_last) issue_row<S>(p, mr, cx, act1, pp + 1, q);
+        __syncthreads();
+        if (in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2) {
+            const Axis ry = make_axis_near(pp - 2, p.ny, wrap_y);
+            finish_node<S, BLOCK, M1>(p, mw, cx, pp - 2, ry.c, s1f, ring1, acc, fring, 0u);
+        }
+        if (in2 && pp - 7 >= y0 && pp - 7 < y1)
+            finish_node<S, BLOCK, M2>(p, mw, cx, pp - 7, pp - 7, s2f, ring2, acc, nullptr, 1u);
+    };
+    for (int pp = p_first;;) {
+        iter(pp, a1, b1, b2, c2);
+        if (++pp > p_last) break;
+        iter(pp, b1, c1, c2, a2);
+        if (++pp > p_last) break;
+        iter(pp, c1, a1, a2, b2);
+        if (++pp > p_last) break;
+    }
+}
+
+template <int S, int BLOCK, int MODE>
+__global__ void __launch_bounds__(BLOCK) k_step2(const KParams<typename Traits<S>::C> p, int per_xcd)
+{
+    using C = typename Traits<S>::C;
+    __shared__ PsiPair<C> ring1[8][BLOCK];
+    __shared__ PsiPair<C> ring2[8][BLOCK];
+    __shared__ typename Traits<S>::raw_t fring[4][2][9][BLOCK];
+    const int b = blockIdx.x;
+    const int unit = p.xcd_slabs ? b : (b & 7) * per_xcd + (b >> 3);
+    if (unit >= p.n_units) return;
+    const PopMem<S> mr = make_mem<S>(p.A, p.N);
+    const PopMem<S> mw = make_mem<S>(p.B, p.N);
+    RedAcc acc;
+    for_unit_segments(p.n_strips, p.n_segs, p.ny, p.xcd_slabs, p.band_order, unit, p.n_units,
+                      [&](int strip, int y0, int y1) {
+                          process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, fring, acc);
+                      });
 }
 
 // One time step (or one field/diagnostic/table pass) of a single run.

@@ -12,17 +12,17 @@ using lbm::KParams;
 using lbm::qw;
 
 // Schedule bits of a tile (lbm_set_tile).
-enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u, SCHED_XCD_SLABS = 4u };
+enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u, SCHED_XCD_SLABS = 4u, SCHED_TWO_STEP = 8u };
 
 // Strips are block - 4 columns wide (balanced over nx), or, with
 // SCHED_ALIGN, the widest multiple of `align_cols` columns that fits, from
 // x = 0, so that every strip's stores start on a 128-byte boundary.
 inline void tile_counts(int block, int seg_rows, int nx, int ny, int *strips, int *segs, unsigned sched = 0,
-                        int align_cols = 32, int *strip_w = nullptr)
+                        int align_cols = 32, int *strip_w = nullptr, int halo = 2)
 {
-    int w = block - 4;
+    int w = block - 2 * halo;
     if ((sched & SCHED_ALIGN) && w >= align_cols) w = (w / align_cols) * align_cols;
-    else if (sched & SCHED_ALIGN) w = block - 4;
+    else if (sched & SCHED_ALIGN) w = block - 2 * halo;
     *strips = (nx + w - 1) / w;
     if (strip_w) *strip_w = (sched & SCHED_ALIGN) ? w : 0;
     const int s = (ny + seg_rows - 1) / seg_rows;

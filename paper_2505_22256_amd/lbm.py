@@ -24,7 +24,7 @@ PERIODIC_X, PERIODIC_Y = 1, 2
 SCHEME_ORIGINAL, E8_COPY_OFF, WALLPSI_SELF, VEL_LITERAL, FORCE_DENSITY = 4, 8, 16, 32, 64
 ROUND_STOCHASTIC = 128
 WALL_FLAT, WALL_CYLINDER = 0, 1
-SCHED_ALIGN, SCHED_BANDS, SCHED_XCD_SLABS = 1, 2, 4
+SCHED_ALIGN, SCHED_BANDS, SCHED_XCD_SLABS, SCHED_TWO_STEP = 1, 2, 4, 8
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 
 _P = ctypes.c_void_p

@@ -1,0 +1,60 @@
+"""Two fused time steps per launch (LBM_SCHED_TWO_STEP) against one step
+per launch: the populations must be bitwise identical, for every storage
+that allows it, with and without stochastic rounding, periodic and walled
+lattices, several tile shapes, odd step counts and fused diagnostics (the
+steps that record diagnostics run alone).  One step per launch is the path
+the FP64 oracle parity tests pin."""
+import numpy as np
+import pytest
+
+from paper_2505_22256_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TWO = 8
+
+
+def _cases():
+    return [W.random_small(11, nx=37, ny=29),
+            W.random_small(12, nx=61, ny=23, flags=W.PERIODIC_X, walls=True),
+            W.random_small(13, nx=300, ny=41, flags=0, walls=True),
+            W.flat_drop(nx=130, ny=47, radius=15, G_ads=-0.25),
+            W.cylinder_drop(G_ads=0.2, nx=96, ny=90, R=14, centre=(48, 34), r_drop=18, drop_centre=(48, 60))]
+
+
+@pytest.mark.parametrize("storage,flags", [(1, 0), (2, 0), (2, 128), (3, 128)])
+def test_two_step_is_bitwise_one_step(lbm_mod, storage, flags):
+    tiles = [(256, 16, TWO), (64, 8, TWO | 2), (128, 0, TWO), (256, 32, TWO | 3), (256, 0, TWO | 4)]
+    for ci, wl in enumerate(_cases()):
+        ref = lbm_mod.lattice_from_workload(wl, storage, flags)
+        ref.set_tile(256, 16, 0)
+        ref.step(37)
+        f_ref = ref.get_populations()
+        for tile in tiles:
+            g = lbm_mod.lattice_from_workload(wl, storage, flags)
+            g.set_tile(*tile)
+            g.step(37)
+            assert np.array_equal(g.get_populations(), f_ref), (ci, tile)
+            g.close()
+
+
+def test_two_step_with_fused_diagnostics(lbm_mod):
+    wl = W.flat_drop()
+    a = lbm_mod.lattice_from_workload(wl, lbm_mod.F32)
+    a.set_diag_interval(5)
+    a.step(23)
+    b = lbm_mod.lattice_from_workload(wl, lbm_mod.F32)
+    b.set_tile(256, 16, TWO | 3)
+    b.set_diag_interval(5)
+    b.step(23)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    da, ta = a.get_diag()
+    db, tb = b.get_diag()
+    assert ta == tb == 20 and np.array_equal(da, db)
+
+
+def test_two_step_refused_for_fp64(lbm_mod):
+    g = lbm_mod.Lattice(20, 20, lbm_mod.F64, 3)
+    with pytest.raises(lbm_mod.LbmError) as e:
+        g.set_tile(256, 16, TWO)
+    assert e.value.code == lbm_mod.EINVAL
