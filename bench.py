@@ -311,7 +311,9 @@ def main():
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
     ap.add_argument("--stochastic", action="store_true", help="stochastic rounding (f16/bf16)")
     ap.add_argument("--diag-every", type=int, default=100)
-    ap.add_argument("--tile", default="auto", help="auto or BLOCK,ROWS[,SCHED]")
+    ap.add_argument("--tile", default="default",
+                    help="default (the library's measured default for the storage), auto (autotune on the "
+                         "workload) or BLOCK,ROWS[,SCHED]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--workload", default="constrictions",
@@ -365,7 +367,9 @@ def main():
     stream = torch.cuda.Stream()
     lat = lbm.lattice_from_workload(wl, storage, flags)
     lat.set_stream(stream.cuda_stream)
-    if args.tile == "auto":
+    if args.tile == "default":
+        block, rows, sched = lat.get_tile()
+    elif args.tile == "auto":
         block, rows, sched = lat.autotune(8)
     else:
         vals = [int(v) for v in args.tile.split(",")]

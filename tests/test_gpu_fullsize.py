@@ -1,13 +1,15 @@
 """Full-size checks on the 16384 x 2048 constriction channel, in the launch
-configuration the benchmark times (autotuned tile), and on the 2048 x 1024
-porous channel of the precision study (FP64, anchored at t = 1000).
+configuration the benchmark times (the library's default tile: two fused
+steps per launch for FP32, one for FP16), and on the 2048 x 1024 porous
+channel of the precision study (FP64, anchored at t = 1000).
 
 The oracle cannot step the whole lattice in test time, so it checks sampled
 nodes one by one: the update of node x from t to t+1 reads only positions
 within Chebyshev distance 3 of x (pull sources at distance 1, whose forces
-read the E8 stencil at distance 2 around them), so the oracle stepped once
-on the 7 x 7 window of f(t) around x (taken from the device) must reproduce
-the device's f(x, t+1).  Whole-lattice properties (mass conservation, no
+read the E8 stencil at distance 2 around them), so the oracle stepped n
+times on the (6n+1) x (6n+1) window of f(t) around x (taken from the device)
+must reproduce the device's f(x, t+n); n is the number of steps the
+device fuses into one launch.  Whole-lattice properties (mass conservation, no
 non-finite value) are checked at full size.
 """
 import numpy as np
@@ -36,16 +38,16 @@ def _samples(wl, n_each=16, seed=7):
     return np.concatenate([pick(fluid), pick(near_idx), pick(seam)])
 
 
-def _oracle_one_step(oracle_mod, wl, f_win, y0, x0, h, w):
+def _oracle_steps(oracle_mod, wl, f_win, y0, x0, h, w, n=1):
     ys = np.arange(y0, y0 + h)
     xs = (x0 + np.arange(w)) % wl.nx
     mask = wl.solid[np.ix_(ys, xs)]
-    o = oracle_mod.Oracle(w, h, 0)  # window edges are never read for the centre node
+    o = oracle_mod.Oracle(w, h, 0)  # the window edges do not reach the centre in n steps
     o.set_geometry(mask)
     o.set_params(wl.G_c, wl.G_ads, wl.tau)
     o.set_body_accel(*wl.accel)
     o.set_populations(f_win)
-    o.step(1)
+    o.step(n)
     return o.get_populations()
 
 
@@ -54,27 +56,29 @@ def _oracle_one_step(oracle_mod, wl, f_win, y0, x0, h, w):
 # deviation |g| <= ~0.45 to half an FP16 ulp (2^-11 relative): 1.2e-4
 # absolute, about 3e-4 of the largest population; 5e-4 allows that.
 @pytest.mark.parametrize("storage,tol", [(1, 2e-6), (2, 5e-4)])
-def test_sampled_nodes_one_step_against_oracle(oracle_mod, lbm_mod, channel, storage, tol):
+def test_sampled_nodes_against_oracle(oracle_mod, lbm_mod, channel, storage, tol):
     wl = channel
     g = lbm_mod.lattice_from_workload(wl, storage)
-    g.autotune(2)
+    n = 2 if g.get_tile()[2] & lbm_mod.SCHED_TWO_STEP else 1
+    rad = 3 * n
     g.step(40)
     samples = _samples(wl)
     before = []
     for (y, x) in samples:
-        y0 = max(0, y - 3)
-        h = min(wl.ny, y + 4) - y0
-        before.append((y0, x - 3, h, 7, g.get_populations_window(x - 3, y0, 7, h)))
-    g.step(1)
+        y0 = max(0, y - rad)
+        h = min(wl.ny, y + rad + 1) - y0
+        w = 2 * rad + 1
+        before.append((y0, x - rad, h, w, g.get_populations_window(x - rad, y0, w, h)))
+    g.step(n)  # one launch
     worst = 0.0
     for (y, x), (y0, x0, h, w, f_win) in zip(samples, before):
         after = g.get_populations_window(x, y, 1, 1)[:, :, 0, 0]
-        ref = _oracle_one_step(oracle_mod, wl, f_win, y0, x0, h, w)[:, :, y - y0, 3]
+        ref = _oracle_steps(oracle_mod, wl, f_win, y0, x0, h, w, n)[:, :, y - y0, rad]
         scale = np.max(np.abs(ref))
         err = np.max(np.abs(after - ref)) / scale
         worst = max(worst, err)
         assert err < tol, (int(y), int(x), err)
-    print(f"storage {storage}: worst relative one-step error {worst:.2e} over {len(samples)} nodes")
+    print(f"storage {storage}: worst relative error over {n} step(s) {worst:.2e}, {len(samples)} nodes")
 
 
 def test_porous_fp64_anchor_at_1000_steps(oracle_mod, lbm_mod):
@@ -95,7 +99,7 @@ def test_porous_fp64_anchor_at_1000_steps(oracle_mod, lbm_mod):
     g.step(1)
     for (y, x), (y0, x0, h, w, f_win) in zip(samples, before):
         after = g.get_populations_window(x, y, 1, 1)[:, :, 0, 0]
-        ref = _oracle_one_step(oracle_mod, wl, f_win, y0, x0, h, w)[:, :, y - y0, 3]
+        ref = _oracle_steps(oracle_mod, wl, f_win, y0, x0, h, w)[:, :, y - y0, 3]
         assert np.max(np.abs(after - ref)) <= 1e-12 * np.max(np.abs(ref)), (int(y), int(x))
     m = g.reduce()
     assert m[7] == 0
@@ -104,7 +108,7 @@ def test_porous_fp64_anchor_at_1000_steps(oracle_mod, lbm_mod):
 def test_full_lattice_mass_and_finiteness(lbm_mod, channel):
     wl = channel
     g = lbm_mod.lattice_from_workload(wl, lbm_mod.F32)
-    g.autotune(2)
+    g.step(1)  # default tile: the benchmark configuration
     m0 = g.reduce()
     g.step(200)
     m1 = g.reduce()
