@@ -200,12 +200,14 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * first, so concurrent workgroups cover whole rows; LBM_SCHED_XCD_SLABS
  * gives each of the 8 XCDs one contiguous slab of rows, one workgroup per
  * strip marching down it (seg_rows is ignored).  LBM_SCHED_TWO_STEP (FP32,
- * FP16, BF16) fuses two time steps per launch: the first step's
+ * FP16, BF16; block 64 or 128) fuses two time steps per launch: the first step's
  * post-collision rows stay in LDS and the second step pulls them from
  * there, so HBM is read and written once per two steps (strips lose 5
- * columns of halo on each side instead of 2); steps that record
- * diagnostics and an odd last step run alone.  Results are bitwise those
- * of single steps.  lbm_autotune times the
+ * columns of halo on each side instead of 2); the diagnostics of either
+ * step are recorded in the same launch; an odd last step (and every step
+ * when diagnostics are due every step) runs alone.  Populations are
+ * bitwise those of single steps; diagnostics agree to rounding (the sums
+ * run in another order).  lbm_autotune times the
  * current tile and then every candidate for `steps` steps each on the
  * current state (restoring state and time afterwards); a candidate replaces
  * the best so far only when it is at least 2 % faster, so timing noise does

@@ -14,28 +14,53 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = [os.path.join(CSRC, "lbm_api.hip"), os.path.join(CSRC, "lbm_batch.hip")]
-HEADERS = [os.path.join(CSRC, n) for n in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp",
-                                            "lbm_contact.hpp")] + [os.path.join(ROOT, "include", "lbm.h")]
+BUILD_DIR = os.path.join(PKG, "_build")
+SOURCES = [os.path.join(CSRC, n) for n in ("lbm_api.hip", "lbm_batch.hip", "lbm_launch_f64.hip", "lbm_launch_f32.hip",
+                                         "lbm_launch_f16.hip", "lbm_launch_bf16.hip")]
+HEADERS = [os.path.join(CSRC, n) for n in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp", "lbm_contact.hpp",
+                                            "lbm_launch.hpp", "lbm_launch_impl.hpp")] + [os.path.join(ROOT, "include", "lbm.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
+    """Compile every translation unit (in parallel) and link liblbm.so."""
     srcs = [s for s in SOURCES if os.path.exists(s)]
     if not force and os.path.exists(LIB):
         newest = max(os.path.getmtime(f) for f in srcs + HEADERS)
         if os.path.getmtime(LIB) >= newest:
             return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(BUILD_DIR, os.path.basename(src) + "." + tag + ".o") for src in srcs]
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    procs, pending = [], list(zip(srcs, objs))
+    try:
+        while pending or procs:
+            while pending and len(procs) < jobs:
+                src, obj = pending.pop(0)
+                cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+                procs.append((subprocess.Popen(cmd), src))
+            proc, src = procs.pop(0)
+            if proc.wait() != 0:
+                raise subprocess.CalledProcessError(proc.returncode, src)
+        tmp = LIB + ".tmp" + tag
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    finally:
+        for p, _ in procs:
+            p.kill()
+        for obj in objs:
+            if os.path.exists(obj):
+                os.remove(obj)
     return LIB
 
 

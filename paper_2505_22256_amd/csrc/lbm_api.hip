@@ -3,6 +3,7 @@
 #include "lbm.h"
 #include "lbm_contact.hpp"
 #include "lbm_kernels.hpp"
+#include "lbm_launch.hpp"
 #include "lbm_params.hpp"
 
 #include <algorithm>
@@ -119,33 +120,6 @@ KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int 
 
 int grid_of(int strips, int segs) { return ((strips * segs + 7) / 8) * 8; }
 
-template <int S, int BLOCK, int MODE>
-hipError_t launch_step_t(const KParams<typename Traits<S>::C> &p, hipStream_t st)
-{
-    const int per_xcd = (p.n_units + 7) / 8;
-    hipLaunchKernelGGL((k_step<S, BLOCK, MODE>), dim3(per_xcd * 8), dim3(BLOCK), 0, st, p, per_xcd);
-    return hipGetLastError();
-}
-
-template <int S, int MODE>
-hipError_t launch_step_b(const KParams<typename Traits<S>::C> &p, int block, hipStream_t st)
-{
-    switch (block) {
-    case 64: return launch_step_t<S, 64, MODE>(p, st);
-    case 128: return launch_step_t<S, 128, MODE>(p, st);
-    default: return launch_step_t<S, 256, MODE>(p, st);
-    }
-}
-
-template <int S, int BLOCK>
-int occupancy_of()
-{
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_step<S, BLOCK, M_STORE>, BLOCK, 0) !=
-        hipSuccess)
-        nb = 1;
-    return std::max(nb, 1);
-}
 
 // Workgroups of the step kernel that fit on the device at once.
 template <int S>
@@ -155,30 +129,7 @@ int resident_capacity(lbm_ctx *c, int block)
         hipDeviceProp_t prop;
         c->cus = (hipGetDeviceProperties(&prop, c->device) == hipSuccess) ? prop.multiProcessorCount : 256;
     }
-    const int per_cu = block == 64 ? occupancy_of<S, 64>() : block == 128 ? occupancy_of<S, 128>()
-                                                                           : occupancy_of<S, 256>();
-    return per_cu * c->cus;
-}
-
-// Kinds of pass over the lattice.  P_STEP2 advances two steps.
-enum Pass { P_STEP, P_STEP_REDUCE, P_FIELDS_REDUCE, P_TABLES, P_STEP2 };
-
-template <int S, int BLOCK, int MODE>
-hipError_t launch_step2_t(const KParams<typename Traits<S>::C> &p, hipStream_t st)
-{
-    const int per_xcd = (p.n_units + 7) / 8;
-    hipLaunchKernelGGL((k_step2<S, BLOCK, MODE>), dim3(per_xcd * 8), dim3(BLOCK), 0, st, p, per_xcd);
-    return hipGetLastError();
-}
-
-template <int S, int MODE>
-hipError_t launch_step2_b(const KParams<typename Traits<S>::C> &p, int block, hipStream_t st)
-{
-    switch (block) {
-    case 64: return launch_step2_t<S, 64, MODE>(p, st);
-    case 128: return launch_step2_t<S, 128, MODE>(p, st);
-    default: return launch_step2_t<S, 256, MODE>(p, st);
-    }
+    return step_occupancy<S>(block) * c->cus;
 }
 
 // Launch one pass reading buf[cur].  P_STEP* write buf[cur^1] (the caller
@@ -187,10 +138,11 @@ template <int S>
 int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts)
 {
     using C = typename Traits<S>::C;
-    const bool stepping = pass == P_STEP || pass == P_STEP_REDUCE || pass == P_STEP2;
+    const bool two = pass == P_STEP2 || pass == P_STEP2_RED1 || pass == P_STEP2_RED2;
+    const bool stepping = pass == P_STEP || pass == P_STEP_REDUCE || two;
     const int block = stepping ? c->block : 256;
     const int seg = c->seg_rows > 0 ? c->seg_rows : 64;
-    KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, seg, pass == P_STEP2 ? 5 : 2);
+    KParams<C> p = make_params<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], block, seg, two ? 5 : 2);
     if ((c->sched & SCHED_XCD_SLABS) && stepping) {
         // one unit per (strip, row slab); the grid is 8 * strips so that
         // workgroup b lands on XCD b % 8 = its slab
@@ -206,7 +158,7 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
     }
     const int grid = ((p.n_units + 7) / 8) * 8;
     if (nparts) *nparts = grid;
-    if (pass == P_STEP_REDUCE || pass == P_FIELDS_REDUCE) {
+    if (pass == P_STEP_REDUCE || pass == P_FIELDS_REDUCE || pass == P_STEP2_RED1 || pass == P_STEP2_RED2) {
         int rc = ensure_partials(c, (size_t)grid);
         if (rc) return rc;
         p.partials = c->d_partials;
@@ -220,35 +172,8 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
     p.tab_link = link;
     p.tab_nw = nw;
     p.tab_src = src;
-    hipError_t e = hipSuccess;
-    constexpr bool narrow = S == ST_F16 || S == ST_BF16;
-    const bool sr = narrow && (c->flags & LBM_ROUND_STOCHASTIC);
-    switch (pass) {
-    case P_STEP:
-        if constexpr (narrow)
-            e = sr ? launch_step_b<S, M_STORE | M_SR>(p, block, c->stream) : launch_step_b<S, M_STORE>(p, block, c->stream);
-        else
-            e = launch_step_b<S, M_STORE>(p, block, c->stream);
-        break;
-    case P_STEP_REDUCE:
-        if constexpr (narrow)
-            e = sr ? launch_step_b<S, M_STORE | M_REDUCE | M_SR>(p, block, c->stream)
-                   : launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream);
-        else
-            e = launch_step_b<S, M_STORE | M_REDUCE>(p, block, c->stream);
-        break;
-    case P_STEP2:
-        if constexpr (S == ST_F64) {
-            e = hipErrorInvalidValue;  // refused by lbm_set_tile
-        } else if constexpr (narrow) {
-            e = sr ? launch_step2_b<S, M_STORE | M_SR>(p, block, c->stream) : launch_step2_b<S, M_STORE>(p, block, c->stream);
-        } else {
-            e = launch_step2_b<S, M_STORE>(p, block, c->stream);
-        }
-        break;
-    case P_FIELDS_REDUCE: e = launch_step_t<S, 256, M_FIELDS | M_REDUCE>(p, c->stream); break;
-    case P_TABLES: e = launch_step_t<S, 256, M_TABLES>(p, c->stream); break;
-    }
+    const bool sr = (S == ST_F16 || S == ST_BF16) && (c->flags & LBM_ROUND_STOCHASTIC);
+    const hipError_t e = launch_pass<S>(p, pass, block, sr, c->stream);
     if (e != hipSuccess) return set_err(c, LBM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
@@ -587,10 +512,19 @@ int lbm_step(lbm_ctx *c, int n)
     for (int s = 0; s < n; ++s) {
         const bool diag_now = c->diag_every > 0 && c->t % c->diag_every == 0;
         const bool diag_next = c->diag_every > 0 && (c->t + 1) % c->diag_every == 0;
-        if (two && !diag_now && !diag_next && n - s >= 2) {
-            // two fused steps; a step that records diagnostics runs alone
-            rc = run_pass(c, P_STEP2, nullptr, nullptr, nullptr, nullptr, nullptr);
+        if (two && !(diag_now && diag_next) && n - s >= 2) {
+            // two fused steps, recording the diagnostics of whichever of
+            // them is due
+            const Pass pass = diag_now ? P_STEP2_RED1 : diag_next ? P_STEP2_RED2 : P_STEP2;
+            int nparts = 0;
+            rc = run_pass(c, pass, nullptr, nullptr, nullptr, nullptr, &nparts);
             if (rc) return rc;
+            if (pass != P_STEP2) {
+                hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->d_partials, nparts,
+                                   c->d_out + 16);
+                HIPCHK(c, hipGetLastError());
+                c->diag_t = diag_now ? c->t : c->t + 1;
+            }
             c->cur ^= 1;
             c->t += 2;
             ++s;
@@ -759,6 +693,8 @@ int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
         return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..15");
     if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64)
         return set_err(c, LBM_EINVAL, "two fused steps need FP32, FP16 or BF16 storage");
+    if ((sched & SCHED_TWO_STEP) && block == 256)
+        return set_err(c, LBM_EINVAL, "two fused steps run in 64- or 128-thread strips");
     c->block = block;
     c->seg_rows = seg_rows;
     c->sched = sched;
@@ -808,6 +744,7 @@ int lbm_autotune(lbm_ctx *c, int steps)
             if (rows[ri] > c->ny && ri > 1) continue;
             if (rows[ri] == 0 && (sc & SCHED_BANDS)) continue;  // bands need fixed segments
             if ((sc & SCHED_XCD_SLABS) && ri != 0) continue;   // slabs ignore seg_rows
+            if (tw && blocks[bi] == 256) continue;  // two fused steps: 64- or 128-thread strips
             if (tw) sc |= SCHED_TWO_STEP;
             cb = blocks[bi];
             cr = rows[ri];

@@ -37,7 +37,8 @@ enum : int {
     M_TABLES = 8,  // write link bits and resolved stencil sources
     M_SR = 16,     // stochastic rounding of FP16 / BF16 stores (compile-time)
     M_LDS = 32,    // first of two fused steps: post-collision values to the LDS ring
-    M_TWO = 64     // kernel advances two steps per launch
+    M_TWO = 64,    // kernel advances two steps per launch
+    M_DIAG_FIRST = 128  // two steps: M_REDUCE records the first step (else the second)
 };
 
 // ---------------------------------------------------------------------------

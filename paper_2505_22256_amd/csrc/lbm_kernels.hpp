@@ -699,8 +699,12 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
                                                  FRing<S, BLOCK> fring, RedAcc &acc)
 {
     using C = typename Traits<S>::C;
-    constexpr int M1 = (MODE & M_SR) | M_STORE | M_LDS;
-    constexpr int M2 = (MODE & M_SR) | M_STORE;
+    // diagnostics of step t come from the first step (core nodes only: the
+    // halo is computed twice), those of step t+1 from the second
+    constexpr bool red1 = (MODE & M_REDUCE) && (MODE & M_DIAG_FIRST);
+    constexpr bool red2 = (MODE & M_REDUCE) && !(MODE & M_DIAG_FIRST);
+    constexpr int M1 = (MODE & M_SR) | M_STORE | M_LDS | (red1 ? M_REDUCE : 0);
+    constexpr int M2 = (MODE & M_SR) | M_STORE | (red2 ? M_REDUCE : 0);
     const int tid = threadIdx.x;
     int x0, x1;
     if (p.strip_w > 0) {
@@ -718,6 +722,8 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     const bool in2 = tid >= 5 && tid < w + 5;
     const int p_first = y0 - 5, p_pull_last = y1 + 4, p_last = y1 + 6;
     const bool wrap_y = p.flags & FL_PERIODIC_Y;
+    const bool core_col = tid >= 5 && tid < w + 5;
+    RedAcc halo_acc;  // first-step diagnostics of halo nodes, discarded
 
     RowState<C> a1, b1, c1, a2, b2, c2;
     RawRow<S> q;
@@ -729,7 +735,8 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
         __syncthreads();
         if (in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2) {
             const Axis ry = make_axis_near(pp - 2, p.ny, wrap_y);
-            finish_node<S, BLOCK, M1>(p, mw, cx, pp - 2, ry.c, s1f, ring1, acc, fring, 0u);
+            const bool core = core_col && pp - 2 >= y0 && pp - 2 < y1;
+            finish_node<S, BLOCK, M1>(p, mw, cx, pp - 2, ry.c, s1f, ring1, core ? acc : halo_acc, fring, 0u);
         }
         if (in2 && pp - 7 >= y0 && pp - 7 < y1)
             finish_node<S, BLOCK, M2>(p, mw, cx, pp - 7, pp - 7, s2f, ring2, acc, nullptr, 1u);
@@ -753,14 +760,19 @@ __global__ void __launch_bounds__(BLOCK) k_step2(const KParams<typename Traits<S
     __shared__ typename Traits<S>::raw_t fring[4][2][9][BLOCK];
     const int b = blockIdx.x;
     const int unit = p.xcd_slabs ? b : (b & 7) * per_xcd + (b >> 3);
-    if (unit >= p.n_units) return;
-    const PopMem<S> mr = make_mem<S>(p.A, p.N);
-    const PopMem<S> mw = make_mem<S>(p.B, p.N);
     RedAcc acc;
-    for_unit_segments(p.n_strips, p.n_segs, p.ny, p.xcd_slabs, p.band_order, unit, p.n_units,
-                      [&](int strip, int y0, int y1) {
-                          process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, fring, acc);
-                      });
+    if (unit < p.n_units) {
+        const PopMem<S> mr = make_mem<S>(p.A, p.N);
+        const PopMem<S> mw = make_mem<S>(p.B, p.N);
+        for_unit_segments(p.n_strips, p.n_segs, p.ny, p.xcd_slabs, p.band_order, unit, p.n_units,
+                          [&](int strip, int y0, int y1) {
+                              process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, fring, acc);
+                          });
+    }
+    if (MODE & M_REDUCE) {
+        __syncthreads();
+        block_reduce_write<BLOCK>(acc, p.partials + (long long)b * 8);
+    }
 }
 
 // One time step (or one field/diagnostic/table pass) of a single run.
