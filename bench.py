@@ -131,7 +131,7 @@ def calibration_batch(args):
     stream = torch.cuda.Stream()
     b = lbm.Batch(runs, storage)
     b.set_stream(stream.cuda_stream)
-    tile = b.autotune(2)
+    tile = b.autotune(4)
     b.use_graph(True, 50)
     n_fluid = b.fluid_nodes
     steps = runs[0].steps if args.full else args.steps
@@ -153,7 +153,8 @@ def calibration_batch(args):
            "vs_baseline": None, "dtype": "f64" if storage == lbm.F64 else "f32", "data": "synthetic",
            "config": {"workload": f"calibration batch: {len(runs)} runs, sides 128..512, flat/cylinder, "
                                   f"seed 22256, {args.storage} storage" + (" stochastic rounding" if args.stochastic else ""),
-                      "runs": len(runs), "fluid_nodes": n_fluid, "tile": {"block": tile[0], "seg_rows": tile[1]},
+                      "runs": len(runs), "fluid_nodes": n_fluid,
+                      "tile": {"block": tile[0], "seg_rows": tile[1], "sched": tile[2]},
                       "graph_steps": 50}}
     if args.full:
         th = b.contact_angles()

@@ -257,12 +257,18 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
  * LBM_EINVAL otherwise.) */
 int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows);
 /* Tile of the batched kernel by measurement: times the current tile and
- * then block in {64, 128, 256} x seg_rows in {8, ..., 256} for `steps`
- * steps each (one launch per step, no graph), keeps the fastest (a
- * candidate needs a 2 % margin over the best so far) and restores every
- * run's state and the step counter.  Synchronous. */
+ * then block in {64, 128, 256} x seg_rows in {8, ..., 256}, with one step
+ * per launch and (except FP64) two fused steps, for `steps` steps each (no
+ * graph), keeps the fastest (a candidate needs a 2 % margin over the best
+ * so far) and restores every run's state and the step counter.
+ * Synchronous. */
 int lbm_batch_autotune(lbm_batch *b, int steps);
 int lbm_batch_get_tile(const lbm_batch *b, int *block, int *seg_rows);
+/* LBM_SCHED_TWO_STEP (FP32 / FP16 / BF16, block 64 or 128) fuses two time
+ * steps per launch as for a single lattice; 0 runs one step per launch.
+ * Other bits are LBM_EINVAL.  The autotuner also tries both. */
+int lbm_batch_set_sched(lbm_batch *b, unsigned sched);
+unsigned lbm_batch_get_sched(const lbm_batch *b);
 int lbm_batch_step(lbm_batch *b, int n);
 int lbm_batch_use_graph(lbm_batch *b, int use_graph, int steps_per_graph);
 int lbm_batch_get_fields(lbm_batch *b, int run, double *rho1, double *rho2, double *ux, double *uy);

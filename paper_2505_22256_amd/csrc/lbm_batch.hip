@@ -54,7 +54,9 @@ struct lbm_batch {
     unsigned *d_tick = nullptr;  // step counter read by the batched kernel
     hipStream_t stream = nullptr, own_stream = nullptr;
     bool use_graph = false;
+    bool two = false;       // two fused steps per launch (LBM_SCHED_TWO_STEP)
     int graph_steps = 0;
+    int gflip[2] = {0, 0};  // buffer parity after replaying graph[parity]
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -105,7 +107,7 @@ KParams<C> run_params(const lbm_batch *b, const BatchRun &r, int storage, int bl
     p.nx = r.nx;
     p.ny = r.ny;
     p.flags = r.flags;
-    tile_counts(block, seg_rows, r.nx, r.ny, &p.n_strips, &p.n_segs);
+    tile_counts(block, seg_rows, r.nx, r.ny, &p.n_strips, &p.n_segs, 0, 32, nullptr, b->two ? 5 : 2);
     p.n_units = p.n_strips * p.n_segs;
     p.item0 = r.item0;
     p.N = (long long)r.nx * r.ny;
@@ -124,7 +126,7 @@ int upload_params_t(lbm_batch *b)
     for (int r = 0; r < b->nruns; ++r) {
         BatchRun &br = b->runs[(size_t)r];
         br.item0 = item;
-        tile_counts(b->block, b->seg_rows, br.nx, br.ny, &br.strips, &br.segs);
+        tile_counts(b->block, b->seg_rows, br.nx, br.ny, &br.strips, &br.segs, 0, 32, nullptr, b->two ? 5 : 2);
         item += br.strips * br.segs;
         h[(size_t)r] = run_params<C>(b, br, b->storage, b->block, b->seg_rows, 0);
     }
@@ -170,7 +172,7 @@ hipError_t launch_batch_t(lbm_batch *b, int flip)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, b->stream, b->d_tick);
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, b->stream, b->d_tick, 1u);
     return hipGetLastError();
 }
 
@@ -181,6 +183,42 @@ hipError_t launch_batch_s(lbm_batch *b, int flip)
     case 64: return launch_batch_t<S, 64>(b, flip);
     case 128: return launch_batch_t<S, 128>(b, flip);
     default: return launch_batch_t<S, 256>(b, flip);
+    }
+}
+
+template <int S, int BLOCK>
+hipError_t launch_batch2_t(lbm_batch *b, int flip)
+{
+    using C = typename Traits<S>::C;
+    const int per_xcd = (b->n_items + 7) / 8;
+    const auto *prm = (const KParams<C> *)b->d_params;
+    const auto *tick = (const unsigned *)b->d_tick;
+    bool done = false;
+    if constexpr (S == ST_F16 || S == ST_BF16) {
+        if (b->runs[0].flags & LBM_ROUND_STOCHASTIC) {
+            hipLaunchKernelGGL((k_step2_batch<S, BLOCK, M_STORE | M_SR>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream,
+                               prm, b->nruns, b->n_items, per_xcd, flip, tick);
+            done = true;
+        }
+    }
+    if (!done)
+        hipLaunchKernelGGL((k_step2_batch<S, BLOCK, M_STORE>), dim3(per_xcd * 8), dim3(BLOCK), 0, b->stream, prm,
+                           b->nruns, b->n_items, per_xcd, flip, tick);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, b->stream, b->d_tick, 2u);
+    return hipGetLastError();
+}
+
+// Two fused steps (FP32 / FP16 / BF16, 64- or 128-thread strips).
+hipError_t launch_batch2(lbm_batch *b, int flip)
+{
+    switch (b->storage) {
+    case LBM_F32: return b->block == 64 ? launch_batch2_t<ST_F32, 64>(b, flip) : launch_batch2_t<ST_F32, 128>(b, flip);
+    case LBM_F16: return b->block == 64 ? launch_batch2_t<ST_F16, 64>(b, flip) : launch_batch2_t<ST_F16, 128>(b, flip);
+    case LBM_BF16:
+        return b->block == 64 ? launch_batch2_t<ST_BF16, 64>(b, flip) : launch_batch2_t<ST_BF16, 128>(b, flip);
+    default: return hipErrorInvalidValue;
     }
 }
 
@@ -253,11 +291,29 @@ int fields_run(lbm_batch *b, int r)
     }
 }
 
+// Enqueue `steps` steps reading buffer parity `flip` first (pairs fused when
+// two-step is on); returns the parity the last launch wrote.
+int enqueue_steps(lbm_batch *b, int steps, int flip, hipError_t &e)
+{
+    int s = 0;
+    while (s < steps && e == hipSuccess) {
+        if (b->two && steps - s >= 2) {
+            e = launch_batch2(b, flip);
+            s += 2;
+        } else {
+            e = launch_batch(b, flip);
+            s += 1;
+        }
+        flip ^= 1;
+    }
+    return flip;
+}
+
 int capture_graph(lbm_batch *b, int parity)
 {
     BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int s = 0; s < b->graph_steps && e == hipSuccess; ++s) e = launch_batch(b, (parity + s) & 1);
+    b->gflip[parity] = enqueue_steps(b, b->graph_steps, parity, e);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -427,6 +483,7 @@ int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows)
     if (!b) return LBM_EINVAL;
     if (!(block == 64 || block == 128 || block == 256) || seg_rows < 1)
         return berr(b, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 1 (batches use fixed segments)");
+    if (b->two && block == 256) return berr(b, LBM_EINVAL, "two fused steps run in 64- or 128-thread strips");
     b->block = block;
     b->seg_rows = seg_rows;
     return upload_params(b);
@@ -450,22 +507,27 @@ int lbm_batch_autotune(lbm_batch *b, int steps)
     const int blocks[3] = {64, 128, 256};
     const int rows[6] = {8, 16, 32, 64, 128, 256};
     const int cur_b = b->block, cur_r = b->seg_rows;
+    const bool cur_two = b->two;
     int best_b = cur_b, best_r = cur_r, rc = LBM_OK;
+    bool best_two = cur_two;
     float best_ms = 1e30f;
-    // candidate -1 is the incumbent tile; the rest need a 2 % margin to win
-    for (int cand = -1; cand < 3 * 6 && e == hipSuccess && rc == LBM_OK; ++cand) {
-        const int cb = cand < 0 ? cur_b : blocks[cand / 6], cr = cand < 0 ? cur_r : rows[cand % 6];
+    const int n_two = b->storage == LBM_F64 ? 1 : 2;
+    const int tsteps = steps < 2 ? 2 : steps;  // a fused launch needs two steps
+    // candidate -1 is the incumbent tile; the rest need a 2 % margin to win.
+    // Each block x rows is tried with one step per launch and, except in
+    // FP64, with two fused steps (64- and 128-thread strips).
+    for (int cand = -1; cand < 3 * 6 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
+        const int cb = cand < 0 ? cur_b : blocks[(cand / 6) % 3], cr = cand < 0 ? cur_r : rows[cand % 6];
+        const bool ct = cand < 0 ? cur_two : cand >= 18;
+        if (ct && cb == 256) continue;
         b->block = cb;
         b->seg_rows = cr;
+        b->two = ct;
         rc = upload_params(b);
         if (rc) break;
-        e = launch_batch(b, b->flip);  // warm-up
-        b->flip ^= 1;
+        b->flip = enqueue_steps(b, 2, b->flip, e);  // warm-up
         if (e == hipSuccess) e = hipEventRecord(ev0, b->stream);
-        for (int s = 0; s < steps && e == hipSuccess; ++s) {
-            e = launch_batch(b, b->flip);
-            b->flip ^= 1;
-        }
+        if (e == hipSuccess) b->flip = enqueue_steps(b, tsteps, b->flip, e);
         if (e == hipSuccess) e = hipEventRecord(ev1, b->stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev1);
         float ms = 0;
@@ -474,6 +536,7 @@ int lbm_batch_autotune(lbm_batch *b, int steps)
             best_ms = ms;
             best_b = cb;
             best_r = cr;
+            best_two = ct;
         }
     }
     if (e == hipSuccess) e = hipMemcpyAsync(b->buf[flip0], backup, bytes, hipMemcpyDeviceToDevice, b->stream);
@@ -485,6 +548,7 @@ int lbm_batch_autotune(lbm_batch *b, int steps)
     b->flip = flip0;
     b->block = best_b;
     b->seg_rows = best_r;
+    b->two = best_two;
     const int rc2 = upload_params(b);
     if (rc) return rc;
     if (e != hipSuccess) return berr(b, LBM_EDEVICE, "batch autotune failed: %s", hipGetErrorString(e));
@@ -498,6 +562,20 @@ int lbm_batch_get_tile(const lbm_batch *b, int *block, int *seg_rows)
     *seg_rows = b->seg_rows;
     return LBM_OK;
 }
+
+int lbm_batch_set_sched(lbm_batch *b, unsigned sched)
+{
+    if (!b) return LBM_EINVAL;
+    if (sched & ~(unsigned)SCHED_TWO_STEP) return berr(b, LBM_EINVAL, "batches take LBM_SCHED_TWO_STEP only");
+    const bool two = sched & SCHED_TWO_STEP;
+    if (two && b->storage == LBM_F64) return berr(b, LBM_EINVAL, "two fused steps need FP32, FP16 or BF16 storage");
+    if (two && b->block == 256) return berr(b, LBM_EINVAL, "two fused steps run in 64- or 128-thread strips");
+    BCHK(b, hipStreamSynchronize(b->stream));
+    b->two = two;
+    return upload_params(b);
+}
+
+unsigned lbm_batch_get_sched(const lbm_batch *b) { return b && b->two ? (unsigned)SCHED_TWO_STEP : 0u; }
 
 int lbm_batch_use_graph(lbm_batch *b, int use_graph, int steps_per_graph)
 {
@@ -523,13 +601,12 @@ int lbm_batch_step(lbm_batch *b, int n)
             }
             BCHK(b, hipGraphLaunch(b->gexec[parity], b->stream));
             s += b->graph_steps;
-            b->flip = (b->flip + b->graph_steps) & 1;
+            b->flip = b->gflip[parity];
         }
     }
-    for (; s < n; ++s) {
-        BCHK(b, launch_batch(b, b->flip));
-        b->flip ^= 1;
-    }
+    hipError_t e = hipSuccess;
+    b->flip = enqueue_steps(b, n - s, b->flip, e);
+    BCHK(b, e);
     return LBM_OK;
 }
 

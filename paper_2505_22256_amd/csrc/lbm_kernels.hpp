@@ -822,8 +822,42 @@ k_step_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns,
     process_unit<S, BLOCK, MODE>(p, item - p.item0, p.n_units, ring, acc);
 }
 
+// Two fused steps of every run of a batch (see k_step2).
+template <int S, int BLOCK, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+k_step2_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns, int n_items, int per_xcd, int flip,
+              const unsigned *__restrict__ tick)
+{
+    using C = typename Traits<S>::C;
+    __shared__ PsiPair<C> ring1[8][BLOCK];
+    __shared__ PsiPair<C> ring2[8][BLOCK];
+    __shared__ typename Traits<S>::raw_t fring[4][2][9][BLOCK];
+    const int b = blockIdx.x;
+    const int item = (b & 7) * per_xcd + (b >> 3);
+    if (item >= n_items) return;
+    int lo = 0, hi = nruns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (runs[mid].item0 <= item) lo = mid; else hi = mid - 1;
+    }
+    KParams<C> p = runs[lo];
+    p.tick = *tick;
+    if (flip) {
+        const void *t = p.A;
+        p.A = p.B;
+        p.B = (void *)t;
+    }
+    const PopMem<S> mr = make_mem<S>(p.A, p.N);
+    const PopMem<S> mw = make_mem<S>(p.B, p.N);
+    RedAcc acc;
+    for_unit_segments(p.n_strips, p.n_segs, p.ny, p.xcd_slabs, p.band_order, item - p.item0, p.n_units,
+                      [&](int strip, int y0, int y1) {
+                          process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, fring, acc);
+                      });
+}
+
 // Advance the batch step counter (one thread; graph-capturable).
-static __global__ void k_tick(unsigned *tick) { tick[0] += 1u; }
+static __global__ void k_tick(unsigned *tick, unsigned n) { tick[0] += n; }
 
 // Finalise diagnostics: deterministic compensated (Neumaier) sums over the
 // workgroup partials in a fixed order; one workgroup of 256 threads.

@@ -74,6 +74,8 @@ SIGNATURES = {
     "lbm_batch_set_tile": (_I, [_P, _I, _I]),
     "lbm_batch_autotune": (_I, [_P, _I]),
     "lbm_batch_get_tile": (_I, [_P, _P, _P]),
+    "lbm_batch_set_sched": (_I, [_P, _U]),
+    "lbm_batch_get_sched": (_U, [_P]),
     "lbm_batch_step": (_I, [_P, _I]),
     "lbm_batch_use_graph": (_I, [_P, _I, _I]),
     "lbm_batch_get_fields": (_I, [_P, _I, _P, _P, _P, _P]),
@@ -324,11 +326,18 @@ class Batch:
         self._c(self._L.lbm_batch_get_tile(self.h, ctypes.byref(b), ctypes.byref(r)))
         return b.value, r.value
 
+    def set_sched(self, sched):
+        self._c(self._L.lbm_batch_set_sched(self.h, int(sched)))
+
+    @property
+    def sched(self):
+        return self._L.lbm_batch_get_sched(self.h)
+
     def autotune(self, steps=3):
         """Time the tile candidates on the current state (restored after)
-        and keep the fastest; returns (block, seg_rows)."""
+        and keep the fastest; returns (block, seg_rows, sched)."""
         self._c(self._L.lbm_batch_autotune(self.h, int(steps)))
-        return self.get_tile()
+        return self.get_tile() + (self.sched,)
 
     def use_graph(self, on=True, steps_per_graph=100):
         self._c(self._L.lbm_batch_use_graph(self.h, 1 if on else 0, steps_per_graph))

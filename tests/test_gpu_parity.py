@@ -344,13 +344,16 @@ def _small_runs():
     return runs
 
 
-@pytest.mark.parametrize("storage,flags", [(1, 0), (2, 128), (0, 0)])
-def test_batch_equals_single_runs_bitwise(lbm_mod, storage, flags):
+@pytest.mark.parametrize("storage,flags,two", [(1, 0, False), (2, 128, False), (0, 0, False), (1, 0, True),
+                                                (2, 128, True), (3, 0, True)])
+def test_batch_equals_single_runs_bitwise(lbm_mod, storage, flags, two):
     runs = _small_runs()
     for wl in runs:
         wl.flags |= flags
     b = lbm_mod.Batch(runs, storage)
     b.set_tile(128, 16)
+    if two:
+        b.set_sched(8)  # two fused steps per launch
     b.use_graph(True, 10)
     b.step(57)  # five graph replays and seven single launches
     singles = []
