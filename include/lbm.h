@@ -190,7 +190,7 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * width block - 4 columns) and rows per workgroup segment.  seg_rows = 0
  * is persistent scheduling: one work unit per resident workgroup, each
  * taking an equal share of the strip rows.  Default after lbm_create:
- * FP32 block 128, seg_rows 64, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; FP16 /
+ * FP32 block 128, seg_rows 24, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; FP16 /
  * BF16 block 256, seg_rows 16, LBM_SCHED_BANDS; FP64 block 256, seg_rows
  * 16, LBM_SCHED_ALIGN | LBM_SCHED_BANDS.  Results do not
  * depend on the tile shape (bitwise).  sched bits: LBM_SCHED_ALIGN makes
@@ -257,7 +257,8 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
  * LBM_EINVAL otherwise.) */
 int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows);
 /* Tile of the batched kernel by measurement: times the current tile and
- * then block in {64, 128, 256} x seg_rows in {8, ..., 256}, with one step
+ * then block in {64, 128, 256} x seg_rows in {8, 16, 24, 32, 48, 64, 128,
+ * 256}, with one step
  * per launch and (except FP64) two fused steps, for `steps` steps each (no
  * graph), keeps the fastest (a candidate needs a 2 % margin over the best
  * so far) and restores every run's state and the step counter.

@@ -310,13 +310,13 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
     }
     c->solid.assign((size_t)c->N, 0);
     // measured defaults on the 16384 x 2048 channel: FP32 fuses two steps
-    // per launch (128-thread strips, 64-row segments in row bands); FP16 /
+    // per launch (128-thread strips, 24-row segments in row bands); FP16 /
     // BF16 (issue-bound, no gain from fusing) and FP64 run one step per
     // launch in 16-row segments and row bands, FP64 with 128-byte aligned
     // strips
     if (storage == LBM_F32) {
         c->block = 128;
-        c->seg_rows = 64;
+        c->seg_rows = 24;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
     } else {
         c->block = 256;
@@ -725,7 +725,7 @@ int lbm_autotune(lbm_ctx *c, int steps)
     if (e == hipSuccess) e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     const int blocks[3] = {64, 128, 256};
-    const int rows[8] = {0, 8, 16, 32, 64, 128, 256, 512};
+    const int rows[10] = {0, 8, 16, 24, 32, 48, 64, 128, 256, 512};
     const int cur_b = c->block, cur_r = c->seg_rows;
     const unsigned cur_s = c->sched;
     int best_b = cur_b, best_r = cur_r;
@@ -735,11 +735,11 @@ int lbm_autotune(lbm_ctx *c, int steps)
     // Each block x rows x schedule is tried with one step per launch and,
     // except in FP64, with two fused steps per launch.
     const int n_two = c->storage == LBM_F64 ? 1 : 2;
-    for (int cand = -1; cand < 3 * 8 * 6 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
+    for (int cand = -1; cand < 3 * 10 * 6 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
         int cb = cur_b, cr = cur_r;
         unsigned sc = cur_s;
         if (cand >= 0) {
-            const int tw = cand / 144, bi = (cand / 48) % 3, ri = (cand / 6) % 8;
+            const int tw = cand / 180, bi = (cand / 60) % 3, ri = (cand / 6) % 10;
             sc = (unsigned)(cand % 6);  // 0-3: align/bands bits; 4, 5: XCD slabs (+ align)
             if (rows[ri] > c->ny && ri > 1) continue;
             if (rows[ri] == 0 && (sc & SCHED_BANDS)) continue;  // bands need fixed segments

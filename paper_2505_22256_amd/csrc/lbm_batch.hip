@@ -505,7 +505,7 @@ int lbm_batch_autotune(lbm_batch *b, int steps)
     if (e == hipSuccess) e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     const int blocks[3] = {64, 128, 256};
-    const int rows[6] = {8, 16, 32, 64, 128, 256};
+    const int rows[8] = {8, 16, 24, 32, 48, 64, 128, 256};
     const int cur_b = b->block, cur_r = b->seg_rows;
     const bool cur_two = b->two;
     int best_b = cur_b, best_r = cur_r, rc = LBM_OK;
@@ -516,9 +516,9 @@ int lbm_batch_autotune(lbm_batch *b, int steps)
     // candidate -1 is the incumbent tile; the rest need a 2 % margin to win.
     // Each block x rows is tried with one step per launch and, except in
     // FP64, with two fused steps (64- and 128-thread strips).
-    for (int cand = -1; cand < 3 * 6 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
-        const int cb = cand < 0 ? cur_b : blocks[(cand / 6) % 3], cr = cand < 0 ? cur_r : rows[cand % 6];
-        const bool ct = cand < 0 ? cur_two : cand >= 18;
+    for (int cand = -1; cand < 3 * 8 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
+        const int cb = cand < 0 ? cur_b : blocks[(cand / 8) % 3], cr = cand < 0 ? cur_r : rows[cand % 8];
+        const bool ct = cand < 0 ? cur_two : cand >= 24;
         if (ct && cb == 256) continue;
         b->block = cb;
         b->seg_rows = cr;

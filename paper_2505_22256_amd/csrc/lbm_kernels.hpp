@@ -22,7 +22,13 @@
 
 namespace lbm {
 
-__device__ __forceinline__ int ring_slot(int r) { return (r + 8) & 7; }
+// Slot of row r in an LDS ring of RS rows (rows may be a few below zero in
+// the halo of a segment).
+template <int RS = 8> __device__ __forceinline__ int ring_slot(int r)
+{
+    if constexpr ((RS & (RS - 1)) == 0) return r & (RS - 1);
+    else return (r + 64 * RS) % RS;
+}
 
 // Reduction accumulators of one thread (FP64).
 struct RedAcc {
@@ -144,7 +150,7 @@ __device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C
 }
 
 // Process a prefetched row: node state into `st`, psi into the LDS ring.
-template <int S, int BLOCK>
+template <int S, int BLOCK, int RS = 8>
 __device__ __forceinline__ void process_row(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
                                             const Axis &cx, bool col_ok, int r, const RawRow<S> &q,
                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
@@ -157,7 +163,7 @@ __device__ __forceinline__ void process_row(const KParams<typename Traits<S>::C>
     PsiPair<C> ps;
     ps.a = (st.info & 256) ? lds_sentinel<C>() : r1;
     ps.b = (st.info & 256) ? lds_sentinel<C>() : r2;
-    ring[ring_slot(r)][threadIdx.x] = ps;
+    ring[ring_slot<RS>(r)][threadIdx.x] = ps;
 }
 
 template <int S>
@@ -170,7 +176,7 @@ __device__ __forceinline__ void issue_row(const KParams<typename Traits<S>::C> &
 
 // Bulk cohesion sums straight from the LDS ring, pair by pair (the same
 // order and operations as cohesion_sums on a gathered stencil).
-template <class C, int BLOCK>
+template <class C, int BLOCK, int RS = 8>
 __device__ __forceinline__ void cohesion_sums_lds(PsiPair<C> (*ring)[BLOCK], int y, int tid, C &s1x, C &s1y, C &s2x,
                                                   C &s2y)
 {
@@ -180,8 +186,8 @@ __device__ __forceinline__ void cohesion_sums_lds(PsiPair<C> (*ring)[BLOCK], int
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int n = 4 * g + h, o = n + 2;
-            const PsiPair<C> a = ring[ring_slot(y + sy(n))][tid + sx(n)];
-            const PsiPair<C> b = ring[ring_slot(y + sy(o))][tid + sx(o)];
+            const PsiPair<C> a = ring[ring_slot<RS>(y + sy(n))][tid + sx(n)];
+            const PsiPair<C> b = ring[ring_slot<RS>(y + sy(o))][tid + sx(o)];
             const C cx = (C)(e8wn(n) * sx(n));
             const C cy = (C)(e8wn(n) * sy(n));
             const C d1 = a.a - b.a;
@@ -197,11 +203,11 @@ __device__ __forceinline__ void cohesion_sums_lds(PsiPair<C> (*ring)[BLOCK], int
 // first-layer position reads zero (or psi(x) under WALLPSI_SELF); an
 // unavailable second-layer position reads what its Table 1 partner
 // resolves to (zero under E8_COPY_OFF).  Same rules as apply_wall_rules.
-template <class C, int BLOCK>
+template <class C, int BLOCK, int RS = 8>
 __device__ __forceinline__ PsiPair<C> resolve_position(PsiPair<C> (*vr)[BLOCK], int n, int y, int tid,
                                                        C r1, C r2, unsigned flags, bool &unavailable)
 {
-    const PsiPair<C> v = vr[ring_slot(y + sy(n))][tid + sx(n)];
+    const PsiPair<C> v = vr[ring_slot<RS>(y + sy(n))][tid + sx(n)];
     unavailable = lds_sent(v.a);
     if (!unavailable) return v;
     PsiPair<C> self, zero;
@@ -213,14 +219,14 @@ __device__ __forceinline__ PsiPair<C> resolve_position(PsiPair<C> (*vr)[BLOCK], 
     if (n < 8) return first_rule;
     if (flags & FL_COPY_OFF) return zero;
     const int m = table1(n);
-    const PsiPair<C> w = vr[ring_slot(y + sy(m))][tid + sx(m)];
+    const PsiPair<C> w = vr[ring_slot<RS>(y + sy(m))][tid + sx(m)];
     return lds_sent(w.a) ? first_rule : w;
 }
 
 // Cohesion and adhesion sums at a node with unavailable stencil positions:
 // the same pair order as cohesion_sums / adhesion_vector, positions
 // resolved by the wall rules, S(x) from the unavailable positions.
-template <class C, int BLOCK>
+template <class C, int BLOCK, int RS = 8>
 __device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int tid, C r1, C r2, unsigned flags,
                                           C &s1x, C &s1y, C &s2x, C &s2y, C &Sx, C &Sy, uint32_t &unav)
 {
@@ -236,8 +242,8 @@ __device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int ti
         for (int h = 0; h < 2; ++h) {
             const int n = 4 * g + h, o = n + 2;
             bool un, uo;
-            const PsiPair<C> a = resolve_position<C, BLOCK>(vr, n, y, tid, r1, r2, flags, un);
-            const PsiPair<C> b = resolve_position<C, BLOCK>(vr, o, y, tid, r1, r2, flags, uo);
+            const PsiPair<C> a = resolve_position<C, BLOCK, RS>(vr, n, y, tid, r1, r2, flags, un);
+            const PsiPair<C> b = resolve_position<C, BLOCK, RS>(vr, o, y, tid, r1, r2, flags, uo);
             unav |= ((uint32_t)un << n) | ((uint32_t)uo << o);
             const C cx = (C)(e8wn(n) * sx(n));
             const C cy = (C)(e8wn(n) * sy(n));
@@ -252,13 +258,13 @@ __device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int ti
 
 // Finish node (x, y) of an interior column: stencil, forces, velocity,
 // collision and the selected outputs.
-template <int S, int BLOCK, int MODE>
+template <int S, int BLOCK, int MODE, int RS = 8>
 __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mw,
                                             const Axis &cx, int y, int yw,
                                             const RowState<typename Traits<S>::C> &st,
                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc,
                                             typename Traits<S>::raw_t (*fring)[2][9][BLOCK] = nullptr,
-                                            unsigned dtick = 0)
+                                            unsigned dtick = 0, int fslot = 0)
 {
     using T = Traits<S>;
     using C = typename T::C;
@@ -273,7 +279,7 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
 #pragma unroll
             for (int k = 0; k < 2; ++k)
 #pragma unroll
-                for (int i = 0; i < 9; ++i) fring[y & 3][k][i][tid] = T::sentinel();
+                for (int i = 0; i < 9; ++i) fring[fslot][k][i][tid] = T::sentinel();
         }
         if (MODE & M_FIELDS) {
             p.out_rho1[node] = 0.0;
@@ -288,7 +294,7 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         return;
     }
 
-    const PsiPair<C> ctr = ring[ring_slot(y)][tid];
+    const PsiPair<C> ctr = ring[ring_slot<RS>(y)][tid];
     const C r1 = ctr.a, r2 = ctr.b;
 
     // first moments j_k = sum_i f_i e_i (Eq. 4), definition order; the
@@ -316,18 +322,18 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
     // E8 cohesion sums (Eq. 8); a sentinel (unavailable position) turns
     // them into NaN and selects the wall path
     C s1x, s1y, s2x, s2y;
-    cohesion_sums_lds<C, BLOCK>(ring, y, tid, s1x, s1y, s2x, s2y);
+    cohesion_sums_lds<C, BLOCK, RS>(ring, y, tid, s1x, s1y, s2x, s2y);
     uint32_t unav = 0;
     C Sx = 0, Sy = 0;
     const bool near = __builtin_isnan(s1x + s1y + s2x + s2y);
     if (near) {
-        wall_sums<C, BLOCK>(ring, y, tid, r1, r2, p.flags, s1x, s1y, s2x, s2y, Sx, Sy, unav);
+        wall_sums<C, BLOCK, RS>(ring, y, tid, r1, r2, p.flags, s1x, s1y, s2x, s2y, Sx, Sy, unav);
     }
 
     if (MODE & M_TABLES) {
         unav = 0;
 #pragma unroll
-        for (int n = 0; n < 24; ++n) unav |= (uint32_t)lds_sent(ring[ring_slot(y + sy(n))][tid + sx(n)].a) << n;
+        for (int n = 0; n < 24; ++n) unav |= (uint32_t)lds_sent(ring[ring_slot<RS>(y + sy(n))][tid + sx(n)].a) << n;
         p.tab_link[node] = (uint8_t)(st.info & 255);
         p.tab_nw[node] = unav ? 1 : 0;
         if (unav) {
@@ -467,8 +473,8 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         if constexpr (MODE & M_LDS) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                fring[y & 3][0][i][tid] = out[0][i];
-                fring[y & 3][1][i][tid] = out[1][i];
+                fring[fslot][0][i][tid] = out[0][i];
+                fring[fslot][1][i][tid] = out[1][i];
             }
         } else {
 #pragma unroll
@@ -632,26 +638,33 @@ __device__ __forceinline__ void process_unit(const KParams<typename Traits<S>::C
 // ---------------------------------------------------------------------------
 // Two fused time steps per launch (temporal blocking).  The first step runs
 // exactly the code of the single step but keeps its post-collision rows in
-// an LDS ring instead of HBM; the second step pulls from that ring, five
-// rows behind, and writes HBM.  HBM then sees one read and one write of the
-// populations per two steps (plus a wider halo: 5 columns and 5 rows on
-// each side instead of 2), and the result is bitwise that of two single
-// steps.
+// an LDS ring instead of HBM; the second step pulls from that ring and
+// writes HBM.  HBM then sees one read and one write of the populations per
+// two steps (plus a wider halo: 5 columns and 5 rows on each side instead of
+// 2), and the result is bitwise that of two single steps.  The rings are as
+// short as the schedule allows (3 rows of post-collision values, 5 rows of
+// psi per step), so that four 128-thread workgroups fit a CU's LDS.
 // ---------------------------------------------------------------------------
+constexpr int TWO_FR = 3;  // rows in the post-collision ring
+constexpr int TWO_PR = 5;  // rows in each psi ring
+
 template <int S, int BLOCK>
 using FRing = typename Traits<S>::raw_t (*)[2][9][BLOCK];
+
+__device__ __forceinline__ int fr_slot(int r) { return ring_slot<TWO_FR>(r); }
 
 // Pull f(x, t+1) = f*(x - e_i, t) of row r from the ring (lane = column).
 template <int S, int BLOCK>
 __device__ __forceinline__ void issue_row_lds(FRing<S, BLOCK> fring, int r, RawRow<S> &q)
 {
     const int tid = threadIdx.x;
+    const int sl[3] = {fr_slot(r - 1), fr_slot(r), fr_slot(r + 1)};
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int src = tid - qx(i);
         const bool in = src >= 0 && src < BLOCK;
         const int lane = in ? src : tid;
-        const int slot = (r - qy(i)) & 3;
+        const int slot = sl[1 - qy(i)];
         q.v[0][i] = in ? fring[slot][0][i][lane] : Traits<S>::sentinel();
         q.v[1][i] = in ? fring[slot][1][i][lane] : Traits<S>::sentinel();
     }
@@ -676,21 +689,24 @@ __device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>
     const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
     RawRow<S> q;
     issue_row_lds<S, BLOCK>(fring, r, q);
-    const LdsReload<S, BLOCK> reload{fring, r & 3, (int)threadIdx.x};
+    const LdsReload<S, BLOCK> reload{fring, fr_slot(r), (int)threadIdx.x};
     C r1 = 0, r2 = 0;
     process_node_src<S>(p, reload, cx, ry, col_ok && ry.ok, q, st, r1, r2);
     PsiPair<C> ps;
     ps.a = (st.info & 256) ? lds_sentinel<C>() : r1;
     ps.b = (st.info & 256) ? lds_sentinel<C>() : r2;
-    ring[ring_slot(r)][threadIdx.x] = ps;
+    ring[ring_slot<TWO_PR>(r)][threadIdx.x] = ps;
 }
 
-// Rows [y0, y1) of a strip, two steps.  Iteration p: step 1 processes row p
-// (pulled from HBM), step 2 processes row p - 5 (pulled from the ring), the
-// loads of row p + 1 are issued, one barrier, then step 1 finishes row p - 2
-// into the ring and step 2 finishes row p - 7 into HBM.  Lanes cover columns
-// x0-5 .. x1+4: step 1 needs psi(t) there, finishes x0-3 .. x1+2; step 2
-// needs psi(t+1) on x0-2 .. x1+1 and finishes x0 .. x1-1.
+// Rows [y0, y1) of a strip, two steps.  Iteration p (three barriers):
+//   1. step 1 processes row p (pulled from HBM), the loads of row p + 1 go out;
+//   2. step 1 finishes row p - 2 into the post-collision ring;
+//   3. step 2 processes row p - 3 (pulled from that ring);
+//   4. step 2 finishes row p - 5 into HBM.
+// Lanes cover columns x0-5 .. x1+4: step 1 needs psi(t) there and finishes
+// x0-3 .. x1+2; step 2 needs psi(t+1) on x0-2 .. x1+1 and finishes
+// x0 .. x1-1.  Rows: step 1 pulls y0-5 .. y1+4 and finishes y0-3 .. y1+2;
+// step 2 processes y0-2 .. y1+1 and finishes y0 .. y1-1.
 template <int S, int BLOCK, int MODE>
 __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mr,
                                                  const PopMem<S> &mw, int strip, int y0, int y1,
@@ -720,7 +736,7 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     const bool in1 = tid >= 2 && tid < w + 8;
     const bool act2 = tid >= 3 && tid < w + 7 && cx.ok;
     const bool in2 = tid >= 5 && tid < w + 5;
-    const int p_first = y0 - 5, p_pull_last = y1 + 4, p_last = y1 + 6;
+    const int p_first = y0 - 5, p_pull_last = y1 + 4, p_last = y1 + 4;
     const bool wrap_y = p.flags & FL_PERIODIC_Y;
     const bool core_col = tid >= 5 && tid < w + 5;
     RedAcc halo_acc;  // first-step diagnostics of halo nodes, discarded
@@ -729,24 +745,30 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     RawRow<S> q;
     issue_row<S>(p, mr, cx, act1, p_first, q);
     auto iter = [&](int pp, RowState<C> &s1w, RowState<C> &s1f, RowState<C> &s2w, RowState<C> &s2f) {
-        if (pp <= p_pull_last) process_row<S, BLOCK>(p, mr, cx, act1, pp, q, ring1, s1w);
-        if (pp - 5 >= y0 - 2 && pp - 5 <= y1 + 1) process_row_lds<S, BLOCK>(p, fring, cx, act2, pp - 5, ring2, s2w);
+        if (pp <= p_pull_last) process_row<S, BLOCK, TWO_PR>(p, mr, cx, act1, pp, q, ring1, s1w);
         if (pp + 1 <= p_pull_last) issue_row<S>(p, mr, cx, act1, pp + 1, q);
         __syncthreads();
         if (in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2) {
             const Axis ry = make_axis_near(pp - 2, p.ny, wrap_y);
             const bool core = core_col && pp - 2 >= y0 && pp - 2 < y1;
-            finish_node<S, BLOCK, M1>(p, mw, cx, pp - 2, ry.c, s1f, ring1, core ? acc : halo_acc, fring, 0u);
+            finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, s1f, ring1, core ? acc : halo_acc, fring, 0u,
+                                              fr_slot(pp - 2));
         }
-        if (in2 && pp - 7 >= y0 && pp - 7 < y1)
-            finish_node<S, BLOCK, M2>(p, mw, cx, pp - 7, pp - 7, s2f, ring2, acc, nullptr, 1u);
+        __syncthreads();
+        if (pp - 3 >= y0 - 2 && pp - 3 <= y1 + 1) process_row_lds<S, BLOCK>(p, fring, cx, act2, pp - 3, ring2, s2w);
+        __syncthreads();
+        if (in2 && pp - 5 >= y0 && pp - 5 < y1)
+            finish_node<S, BLOCK, M2, TWO_PR>(p, mw, cx, pp - 5, pp - 5, s2f, ring2, acc, nullptr, 1u);
     };
+    // state of row r: step 1 in {a1, b1, c1}, step 2 in {a2, b2, c2}, both by
+    // (r - p_first) mod 3; iteration p writes rows p (step 1) and p - 3
+    // (step 2) and finishes rows p - 2 and p - 5
     for (int pp = p_first;;) {
-        iter(pp, a1, b1, b2, c2);
+        iter(pp, a1, b1, a2, b2);
         if (++pp > p_last) break;
-        iter(pp, b1, c1, c2, a2);
+        iter(pp, b1, c1, b2, c2);
         if (++pp > p_last) break;
-        iter(pp, c1, a1, a2, b2);
+        iter(pp, c1, a1, c2, a2);
         if (++pp > p_last) break;
     }
 }
@@ -755,9 +777,9 @@ template <int S, int BLOCK, int MODE>
 __global__ void __launch_bounds__(BLOCK) k_step2(const KParams<typename Traits<S>::C> p, int per_xcd)
 {
     using C = typename Traits<S>::C;
-    __shared__ PsiPair<C> ring1[8][BLOCK];
-    __shared__ PsiPair<C> ring2[8][BLOCK];
-    __shared__ typename Traits<S>::raw_t fring[4][2][9][BLOCK];
+    __shared__ PsiPair<C> ring1[TWO_PR][BLOCK];
+    __shared__ PsiPair<C> ring2[TWO_PR][BLOCK];
+    __shared__ typename Traits<S>::raw_t fring[TWO_FR][2][9][BLOCK];
     const int b = blockIdx.x;
     const int unit = p.xcd_slabs ? b : (b & 7) * per_xcd + (b >> 3);
     RedAcc acc;
@@ -829,9 +851,9 @@ k_step2_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns
               const unsigned *__restrict__ tick)
 {
     using C = typename Traits<S>::C;
-    __shared__ PsiPair<C> ring1[8][BLOCK];
-    __shared__ PsiPair<C> ring2[8][BLOCK];
-    __shared__ typename Traits<S>::raw_t fring[4][2][9][BLOCK];
+    __shared__ PsiPair<C> ring1[TWO_PR][BLOCK];
+    __shared__ PsiPair<C> ring2[TWO_PR][BLOCK];
+    __shared__ typename Traits<S>::raw_t fring[TWO_FR][2][9][BLOCK];
     const int b = blockIdx.x;
     const int item = (b & 7) * per_xcd + (b >> 3);
     if (item >= n_items) return;
