@@ -200,7 +200,7 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * first, so concurrent workgroups cover whole rows; LBM_SCHED_XCD_SLABS
  * gives each of the 8 XCDs one contiguous slab of rows, one workgroup per
  * strip marching down it (seg_rows is ignored).  LBM_SCHED_TWO_STEP (FP32,
- * FP16, BF16; block 64 or 128) fuses two time steps per launch: the first step's
+ * FP16, BF16; any block) fuses two time steps per launch: the first step's
  * post-collision rows stay in LDS and the second step pulls them from
  * there, so HBM is read and written once per two steps (strips lose 5
  * columns of halo on each side instead of 2); the diagnostics of either
@@ -265,7 +265,7 @@ int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows);
  * Synchronous. */
 int lbm_batch_autotune(lbm_batch *b, int steps);
 int lbm_batch_get_tile(const lbm_batch *b, int *block, int *seg_rows);
-/* LBM_SCHED_TWO_STEP (FP32 / FP16 / BF16, block 64 or 128) fuses two time
+/* LBM_SCHED_TWO_STEP (FP32 / FP16 / BF16, any block) fuses two time
  * steps per launch as for a single lattice; 0 runs one step per launch.
  * Other bits are LBM_EINVAL.  The autotuner also tries both. */
 int lbm_batch_set_sched(lbm_batch *b, unsigned sched);

@@ -693,8 +693,6 @@ int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
         return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..15");
     if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64)
         return set_err(c, LBM_EINVAL, "two fused steps need FP32, FP16 or BF16 storage");
-    if ((sched & SCHED_TWO_STEP) && block == 256)
-        return set_err(c, LBM_EINVAL, "two fused steps run in 64- or 128-thread strips");
     c->block = block;
     c->seg_rows = seg_rows;
     c->sched = sched;
@@ -744,7 +742,6 @@ int lbm_autotune(lbm_ctx *c, int steps)
             if (rows[ri] > c->ny && ri > 1) continue;
             if (rows[ri] == 0 && (sc & SCHED_BANDS)) continue;  // bands need fixed segments
             if ((sc & SCHED_XCD_SLABS) && ri != 0) continue;   // slabs ignore seg_rows
-            if (tw && blocks[bi] == 256) continue;  // two fused steps: 64- or 128-thread strips
             if (tw) sc |= SCHED_TWO_STEP;
             cb = blocks[bi];
             cr = rows[ri];

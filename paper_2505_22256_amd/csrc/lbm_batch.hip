@@ -210,14 +210,23 @@ hipError_t launch_batch2_t(lbm_batch *b, int flip)
     return hipGetLastError();
 }
 
-// Two fused steps (FP32 / FP16 / BF16, 64- or 128-thread strips).
+template <int S>
+hipError_t launch_batch2_s(lbm_batch *b, int flip)
+{
+    switch (b->block) {
+    case 64: return launch_batch2_t<S, 64>(b, flip);
+    case 128: return launch_batch2_t<S, 128>(b, flip);
+    default: return launch_batch2_t<S, 256>(b, flip);
+    }
+}
+
+// Two fused steps (FP32 / FP16 / BF16).
 hipError_t launch_batch2(lbm_batch *b, int flip)
 {
     switch (b->storage) {
-    case LBM_F32: return b->block == 64 ? launch_batch2_t<ST_F32, 64>(b, flip) : launch_batch2_t<ST_F32, 128>(b, flip);
-    case LBM_F16: return b->block == 64 ? launch_batch2_t<ST_F16, 64>(b, flip) : launch_batch2_t<ST_F16, 128>(b, flip);
-    case LBM_BF16:
-        return b->block == 64 ? launch_batch2_t<ST_BF16, 64>(b, flip) : launch_batch2_t<ST_BF16, 128>(b, flip);
+    case LBM_F32: return launch_batch2_s<ST_F32>(b, flip);
+    case LBM_F16: return launch_batch2_s<ST_F16>(b, flip);
+    case LBM_BF16: return launch_batch2_s<ST_BF16>(b, flip);
     default: return hipErrorInvalidValue;
     }
 }
@@ -483,7 +492,6 @@ int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows)
     if (!b) return LBM_EINVAL;
     if (!(block == 64 || block == 128 || block == 256) || seg_rows < 1)
         return berr(b, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 1 (batches use fixed segments)");
-    if (b->two && block == 256) return berr(b, LBM_EINVAL, "two fused steps run in 64- or 128-thread strips");
     b->block = block;
     b->seg_rows = seg_rows;
     return upload_params(b);
@@ -515,11 +523,10 @@ int lbm_batch_autotune(lbm_batch *b, int steps)
     const int tsteps = steps < 2 ? 2 : steps;  // a fused launch needs two steps
     // candidate -1 is the incumbent tile; the rest need a 2 % margin to win.
     // Each block x rows is tried with one step per launch and, except in
-    // FP64, with two fused steps (64- and 128-thread strips).
+    // FP64, with two fused steps.
     for (int cand = -1; cand < 3 * 8 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
         const int cb = cand < 0 ? cur_b : blocks[(cand / 8) % 3], cr = cand < 0 ? cur_r : rows[cand % 8];
         const bool ct = cand < 0 ? cur_two : cand >= 24;
-        if (ct && cb == 256) continue;
         b->block = cb;
         b->seg_rows = cr;
         b->two = ct;
@@ -569,7 +576,6 @@ int lbm_batch_set_sched(lbm_batch *b, unsigned sched)
     if (sched & ~(unsigned)SCHED_TWO_STEP) return berr(b, LBM_EINVAL, "batches take LBM_SCHED_TWO_STEP only");
     const bool two = sched & SCHED_TWO_STEP;
     if (two && b->storage == LBM_F64) return berr(b, LBM_EINVAL, "two fused steps need FP32, FP16 or BF16 storage");
-    if (two && b->block == 256) return berr(b, LBM_EINVAL, "two fused steps run in 64- or 128-thread strips");
     BCHK(b, hipStreamSynchronize(b->stream));
     b->two = two;
     return upload_params(b);

@@ -30,6 +30,39 @@ template <int RS = 8> __device__ __forceinline__ int ring_slot(int r)
     else return (r + 64 * RS) % RS;
 }
 
+// Post-collision values of the first of two fused steps, kept in LDS for
+// the second.  They are grouped by how long the second step needs them: the
+// downward directions (4, 7, 8) of a row are pulled by the row below in the
+// same iteration that writes them, the upward ones (2, 5, 6) by the row
+// above one iteration later, and the rest and horizontal directions
+// (0, 1, 3) only by the row itself.  Writing the last two groups only after
+// the second step has read the row before lets the downward and upward
+// groups live in two row slots and the rest/horizontal group in one.
+__host__ __device__ constexpr int fr_gidx(int i) { return i == 0 || i == 2 || i == 4 ? 0 : (i == 1 || i == 5 || i == 7 ? 1 : 2); }
+
+template <int S, int BLOCK> struct FRingMem {
+    typename Traits<S>::raw_t h[2][3][BLOCK];     // directions 0, 1, 3 of one row
+    typename Traits<S>::raw_t d[2][2][3][BLOCK];  // 4, 7, 8 of two rows (slot = row & 1)
+    typename Traits<S>::raw_t u[2][2][3][BLOCK];  // 2, 5, 6 of two rows (slot = row & 1)
+};
+
+// Slot of direction i, component k, of row `row` at column `lane`.
+template <int S, int BLOCK>
+__device__ __forceinline__ typename Traits<S>::raw_t &fr_at(FRingMem<S, BLOCK> *m, int k, int i, int row, int lane)
+{
+    if (qy(i) == 0) return m->h[k][fr_gidx(i)][lane];
+    if (qy(i) < 0) return m->d[row & 1][k][fr_gidx(i)][lane];
+    return m->u[row & 1][k][fr_gidx(i)][lane];
+}
+
+// The rest/horizontal and upward values of the row just finished by the
+// first step, held in registers until the second step has read the
+// previous row.
+template <int S> struct FPending {
+    typename Traits<S>::raw_t h[2][3];
+    typename Traits<S>::raw_t u[2][3];
+};
+
 // Reduction accumulators of one thread (FP64).
 struct RedAcc {
     double m1 = 0, m2 = 0, px = 0, py = 0, umax = 0, rmin = __builtin_inf(), rmax = -__builtin_inf(), bad = 0;
@@ -263,8 +296,8 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
                                             const Axis &cx, int y, int yw,
                                             const RowState<typename Traits<S>::C> &st,
                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc,
-                                            typename Traits<S>::raw_t (*fring)[2][9][BLOCK] = nullptr,
-                                            unsigned dtick = 0, int fslot = 0)
+                                            FRingMem<S, BLOCK> *fring = nullptr, unsigned dtick = 0,
+                                            FPending<S> *pend = nullptr, bool count = true)
 {
     using T = Traits<S>;
     using C = typename T::C;
@@ -275,11 +308,15 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
     const int tid = threadIdx.x;
 
     if (st.info & 256) {  // solid node (or outside the domain)
-        if (MODE & M_LDS) {
+        if constexpr (MODE & M_LDS) {
 #pragma unroll
             for (int k = 0; k < 2; ++k)
 #pragma unroll
-                for (int i = 0; i < 9; ++i) fring[fslot][k][i][tid] = T::sentinel();
+                for (int i = 0; i < 9; ++i) {
+                    if (qy(i) < 0) fr_at<S, BLOCK>(fring, k, i, y, tid) = T::sentinel();
+                    else if (qy(i) == 0) pend->h[k][fr_gidx(i)] = T::sentinel();
+                    else pend->u[k][fr_gidx(i)] = T::sentinel();
+                }
         }
         if (MODE & M_FIELDS) {
             p.out_rho1[node] = 0.0;
@@ -385,7 +422,7 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         p.out_ux[node] = (double)ux;
         p.out_uy[node] = (double)uy;
     }
-    if (MODE & M_REDUCE) {
+    if ((MODE & M_REDUCE) && count) {
         const double d1 = r1, d2 = r2, dux = ux, duy = uy;
         if (!__builtin_isfinite(d1) || !__builtin_isfinite(d2) || !__builtin_isfinite(dux) ||
             !__builtin_isfinite(duy)) {
@@ -472,10 +509,13 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         }
         if constexpr (MODE & M_LDS) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                fring[fslot][0][i][tid] = out[0][i];
-                fring[fslot][1][i][tid] = out[1][i];
-            }
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    if (qy(i) < 0) fr_at<S, BLOCK>(fring, k, i, y, tid) = out[k][i];
+                    else if (qy(i) == 0) pend->h[k][fr_gidx(i)] = out[k][i];
+                    else pend->u[k][fr_gidx(i)] = out[k][i];
+                }
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -486,37 +526,62 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
     }
 }
 
-// Block-wide deterministic reduction of the 8 accumulators; thread 0 writes
-// the workgroup's partial record.
+// Block-wide deterministic reduction of the 8 accumulators: a fixed
+// butterfly of cross-lane exchanges inside each 64-lane wavefront (every
+// lane ends with the same value, since a + b == b + a exactly), then the
+// wavefront results in wavefront order; thread 0 writes the workgroup's
+// partial record.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        const double o = __shfl_xor(v, m, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        const double o = __shfl_xor(v, m, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
 template <int BLOCK>
 __device__ void block_reduce_write(RedAcc acc, double *out)
 {
-    __shared__ double red[8][BLOCK];
+    constexpr int NW = BLOCK / 64;
+    __shared__ double red[8][NW];
+    const double r[8] = {wave_sum(acc.m1), wave_sum(acc.m2), wave_sum(acc.px),   wave_sum(acc.py),
+                         wave_max(acc.umax), wave_min(acc.rmin), wave_max(acc.rmax), wave_sum(acc.bad)};
     const int t = threadIdx.x;
-    red[0][t] = acc.m1;
-    red[1][t] = acc.m2;
-    red[2][t] = acc.px;
-    red[3][t] = acc.py;
-    red[4][t] = acc.umax;
-    red[5][t] = acc.rmin;
-    red[6][t] = acc.rmax;
-    red[7][t] = acc.bad;
+    if ((t & 63) == 0)
+        for (int q = 0; q < 8; ++q) red[q][t >> 6] = r[q];
     __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            red[0][t] += red[0][t + s];
-            red[1][t] += red[1][t + s];
-            red[2][t] += red[2][t + s];
-            red[3][t] += red[3][t + s];
-            red[4][t] = red[4][t] > red[4][t + s] ? red[4][t] : red[4][t + s];
-            red[5][t] = red[5][t] < red[5][t + s] ? red[5][t] : red[5][t + s];
-            red[6][t] = red[6][t] > red[6][t + s] ? red[6][t] : red[6][t + s];
-            red[7][t] += red[7][t + s];
+    if (t == 0) {
+        double v[8];
+        for (int q = 0; q < 8; ++q) v[q] = red[q][0];
+        for (int w = 1; w < NW; ++w) {
+            v[0] += red[0][w];
+            v[1] += red[1][w];
+            v[2] += red[2][w];
+            v[3] += red[3][w];
+            v[4] = red[4][w] > v[4] ? red[4][w] : v[4];
+            v[5] = red[5][w] < v[5] ? red[5][w] : v[5];
+            v[6] = red[6][w] > v[6] ? red[6][w] : v[6];
+            v[7] += red[7][w];
         }
-        __syncthreads();
+        for (int q = 0; q < 8; ++q) out[q] = v[q];
     }
-    if (t == 0)
-        for (int q = 0; q < 8; ++q) out[q] = red[q][0];
 }
 
 // One segment: rows [y0, y1) of a strip.  The psi of rows y0-2 .. y1+1
@@ -638,49 +703,42 @@ __device__ __forceinline__ void process_unit(const KParams<typename Traits<S>::C
 // ---------------------------------------------------------------------------
 // Two fused time steps per launch (temporal blocking).  The first step runs
 // exactly the code of the single step but keeps its post-collision rows in
-// an LDS ring instead of HBM; the second step pulls from that ring and
+// LDS (FRingMem) instead of HBM; the second step pulls from there and
 // writes HBM.  HBM then sees one read and one write of the populations per
 // two steps (plus a wider halo: 5 columns and 5 rows on each side instead of
-// 2), and the result is bitwise that of two single steps.  The rings are as
-// short as the schedule allows (3 rows of post-collision values, 5 rows of
-// psi per step), so that four 128-thread workgroups fit a CU's LDS.
+// 2), and the result is bitwise that of two single steps.  The LDS holds
+// 5 rows' worth of post-collision values (two rows of the downward and
+// upward groups, one of the rest) and 5 rows of psi per step, so that six
+// 128-thread FP32 workgroups fit a CU's LDS.
 // ---------------------------------------------------------------------------
-constexpr int TWO_FR = 3;  // rows in the post-collision ring
 constexpr int TWO_PR = 5;  // rows in each psi ring
 
+// Pull f(x, t+1) = f*(x - e_i, t) of row r from the LDS (lane = column).
 template <int S, int BLOCK>
-using FRing = typename Traits<S>::raw_t (*)[2][9][BLOCK];
-
-__device__ __forceinline__ int fr_slot(int r) { return ring_slot<TWO_FR>(r); }
-
-// Pull f(x, t+1) = f*(x - e_i, t) of row r from the ring (lane = column).
-template <int S, int BLOCK>
-__device__ __forceinline__ void issue_row_lds(FRing<S, BLOCK> fring, int r, RawRow<S> &q)
+__device__ __forceinline__ void issue_row_lds(FRingMem<S, BLOCK> *fring, int r, RawRow<S> &q)
 {
     const int tid = threadIdx.x;
-    const int sl[3] = {fr_slot(r - 1), fr_slot(r), fr_slot(r + 1)};
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int src = tid - qx(i);
         const bool in = src >= 0 && src < BLOCK;
         const int lane = in ? src : tid;
-        const int slot = sl[1 - qy(i)];
-        q.v[0][i] = in ? fring[slot][0][i][lane] : Traits<S>::sentinel();
-        q.v[1][i] = in ? fring[slot][1][i][lane] : Traits<S>::sentinel();
+        q.v[0][i] = in ? fr_at<S, BLOCK>(fring, 0, i, r - qy(i), lane) : Traits<S>::sentinel();
+        q.v[1][i] = in ? fr_at<S, BLOCK>(fring, 1, i, r - qy(i), lane) : Traits<S>::sentinel();
     }
 }
 
 template <int S, int BLOCK> struct LdsReload {
-    FRing<S, BLOCK> fring;
-    int slot, lane;
+    FRingMem<S, BLOCK> *fring;
+    int row, lane;
     __device__ __forceinline__ typename Traits<S>::raw_t operator()(int k, int i) const
     {
-        return fring[slot][k][i][lane];
+        return fr_at<S, BLOCK>(fring, k, i, row, lane);
     }
 };
 
 template <int S, int BLOCK>
-__device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>::C> &p, FRing<S, BLOCK> fring,
+__device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>::C> &p, FRingMem<S, BLOCK> *fring,
                                                 const Axis &cx, bool col_ok, int r,
                                                 PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
                                                 RowState<typename Traits<S>::C> &st)
@@ -689,7 +747,7 @@ __device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>
     const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
     RawRow<S> q;
     issue_row_lds<S, BLOCK>(fring, r, q);
-    const LdsReload<S, BLOCK> reload{fring, fr_slot(r), (int)threadIdx.x};
+    const LdsReload<S, BLOCK> reload{fring, r, (int)threadIdx.x};
     C r1 = 0, r2 = 0;
     process_node_src<S>(p, reload, cx, ry, col_ok && ry.ok, q, st, r1, r2);
     PsiPair<C> ps;
@@ -700,9 +758,11 @@ __device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>
 
 // Rows [y0, y1) of a strip, two steps.  Iteration p (three barriers):
 //   1. step 1 processes row p (pulled from HBM), the loads of row p + 1 go out;
-//   2. step 1 finishes row p - 2 into the post-collision ring;
-//   3. step 2 processes row p - 3 (pulled from that ring);
-//   4. step 2 finishes row p - 5 into HBM.
+//   2. step 1 finishes row p - 2: its downward directions go to LDS, the
+//      others to registers;
+//   3. step 2 processes row p - 3 (pulled from LDS);
+//   4. the held directions of row p - 2 go to LDS, and step 2 finishes
+//      row p - 5 into HBM.
 // Lanes cover columns x0-5 .. x1+4: step 1 needs psi(t) there and finishes
 // x0-3 .. x1+2; step 2 needs psi(t+1) on x0-2 .. x1+1 and finishes
 // x0 .. x1-1.  Rows: step 1 pulls y0-5 .. y1+4 and finishes y0-3 .. y1+2;
@@ -712,7 +772,7 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
                                                  const PopMem<S> &mw, int strip, int y0, int y1,
                                                  PsiPair<typename Traits<S>::C> (*ring1)[BLOCK],
                                                  PsiPair<typename Traits<S>::C> (*ring2)[BLOCK],
-                                                 FRing<S, BLOCK> fring, RedAcc &acc)
+                                                 FRingMem<S, BLOCK> *fring, RedAcc &acc)
 {
     using C = typename Traits<S>::C;
     // diagnostics of step t come from the first step (core nodes only: the
@@ -739,7 +799,6 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     const int p_first = y0 - 5, p_pull_last = y1 + 4, p_last = y1 + 4;
     const bool wrap_y = p.flags & FL_PERIODIC_Y;
     const bool core_col = tid >= 5 && tid < w + 5;
-    RedAcc halo_acc;  // first-step diagnostics of halo nodes, discarded
 
     RowState<C> a1, b1, c1, a2, b2, c2;
     RawRow<S> q;
@@ -748,15 +807,25 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
         if (pp <= p_pull_last) process_row<S, BLOCK, TWO_PR>(p, mr, cx, act1, pp, q, ring1, s1w);
         if (pp + 1 <= p_pull_last) issue_row<S>(p, mr, cx, act1, pp + 1, q);
         __syncthreads();
-        if (in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2) {
+        const bool fin1 = in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2;
+        FPending<S> pend;
+        if (fin1) {
             const Axis ry = make_axis_near(pp - 2, p.ny, wrap_y);
             const bool core = core_col && pp - 2 >= y0 && pp - 2 < y1;
-            finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, s1f, ring1, core ? acc : halo_acc, fring, 0u,
-                                              fr_slot(pp - 2));
+            finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, s1f, ring1, acc, fring, 0u, &pend, core);
         }
         __syncthreads();
         if (pp - 3 >= y0 - 2 && pp - 3 <= y1 + 1) process_row_lds<S, BLOCK>(p, fring, cx, act2, pp - 3, ring2, s2w);
         __syncthreads();
+        if (fin1) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    fring->h[k][j][tid] = pend.h[k][j];
+                    fring->u[(pp - 2) & 1][k][j][tid] = pend.u[k][j];
+                }
+        }
         if (in2 && pp - 5 >= y0 && pp - 5 < y1)
             finish_node<S, BLOCK, M2, TWO_PR>(p, mw, cx, pp - 5, pp - 5, s2f, ring2, acc, nullptr, 1u);
     };
@@ -779,7 +848,7 @@ __global__ void __launch_bounds__(BLOCK) k_step2(const KParams<typename Traits<S
     using C = typename Traits<S>::C;
     __shared__ PsiPair<C> ring1[TWO_PR][BLOCK];
     __shared__ PsiPair<C> ring2[TWO_PR][BLOCK];
-    __shared__ typename Traits<S>::raw_t fring[TWO_FR][2][9][BLOCK];
+    __shared__ FRingMem<S, BLOCK> fring;
     const int b = blockIdx.x;
     const int unit = p.xcd_slabs ? b : (b & 7) * per_xcd + (b >> 3);
     RedAcc acc;
@@ -788,7 +857,7 @@ __global__ void __launch_bounds__(BLOCK) k_step2(const KParams<typename Traits<S
         const PopMem<S> mw = make_mem<S>(p.B, p.N);
         for_unit_segments(p.n_strips, p.n_segs, p.ny, p.xcd_slabs, p.band_order, unit, p.n_units,
                           [&](int strip, int y0, int y1) {
-                              process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, fring, acc);
+                              process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, &fring, acc);
                           });
     }
     if (MODE & M_REDUCE) {
@@ -853,7 +922,7 @@ k_step2_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns
     using C = typename Traits<S>::C;
     __shared__ PsiPair<C> ring1[TWO_PR][BLOCK];
     __shared__ PsiPair<C> ring2[TWO_PR][BLOCK];
-    __shared__ typename Traits<S>::raw_t fring[TWO_FR][2][9][BLOCK];
+    __shared__ FRingMem<S, BLOCK> fring;
     const int b = blockIdx.x;
     const int item = (b & 7) * per_xcd + (b >> 3);
     if (item >= n_items) return;
@@ -874,7 +943,7 @@ k_step2_batch(const KParams<typename Traits<S>::C> *__restrict__ runs, int nruns
     RedAcc acc;
     for_unit_segments(p.n_strips, p.n_segs, p.ny, p.xcd_slabs, p.band_order, item - p.item0, p.n_units,
                       [&](int strip, int y0, int y1) {
-                          process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, fring, acc);
+                          process_segment2<S, BLOCK, MODE>(p, mr, mw, strip, y0, y1, ring1, ring2, &fring, acc);
                       });
 }
 

@@ -36,12 +36,14 @@ hipError_t launch_step2_t(const KParams<typename Traits<S>::C> &p, hipStream_t s
     return hipGetLastError();
 }
 
-// Two fused steps run in 64- or 128-thread strips (the LDS ring of a
-// 256-thread strip would leave one workgroup per CU).
 template <int S, int MODE>
 hipError_t launch_step2_b(const KParams<typename Traits<S>::C> &p, int block, hipStream_t st)
 {
-    return block == 64 ? launch_step2_t<S, 64, MODE>(p, st) : launch_step2_t<S, 128, MODE>(p, st);
+    switch (block) {
+    case 64: return launch_step2_t<S, 64, MODE>(p, st);
+    case 128: return launch_step2_t<S, 128, MODE>(p, st);
+    default: return launch_step2_t<S, 256, MODE>(p, st);
+    }
 }
 
 template <int S>

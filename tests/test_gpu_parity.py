@@ -344,14 +344,15 @@ def _small_runs():
     return runs
 
 
-@pytest.mark.parametrize("storage,flags,two", [(1, 0, False), (2, 128, False), (0, 0, False), (1, 0, True),
-                                                (2, 128, True), (3, 0, True)])
-def test_batch_equals_single_runs_bitwise(lbm_mod, storage, flags, two):
+@pytest.mark.parametrize("storage,flags,two,block", [(1, 0, False, 128), (2, 128, False, 128), (0, 0, False, 128),
+                                                      (1, 0, True, 128), (2, 128, True, 128), (3, 0, True, 128),
+                                                      (1, 0, True, 256)])
+def test_batch_equals_single_runs_bitwise(lbm_mod, storage, flags, two, block):
     runs = _small_runs()
     for wl in runs:
         wl.flags |= flags
     b = lbm_mod.Batch(runs, storage)
-    b.set_tile(128, 16)
+    b.set_tile(block, 16)
     if two:
         b.set_sched(8)  # two fused steps per launch
     b.use_graph(True, 10)
