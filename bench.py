@@ -304,6 +304,85 @@ def scheme_comparison(args):
                                 f"{args.storage} storage, G_w2 = G_c = 0.9, delta = 0.8", "rows": rows}), flush=True)
 
 
+def _timed_steps(lat, stream, steps, warmup):
+    import torch
+    with torch.cuda.stream(stream):
+        lat.step(warmup)
+        lat.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        lat.step(steps)
+        ev1.record(stream)
+        ev1.synchronize()
+    return ev0.elapsed_time(ev1)
+
+
+def open_channel(args):
+    """The constriction channel with its x edges opened (Zou-He inlet with a
+    Poiseuille profile at x = 0, outflow at x = nx-1) against the periodic
+    channel, same storage and tile: the cost of the open boundaries on the
+    hot path."""
+    import torch
+    storage = STORAGES[args.storage]
+    steps = args.steps if args.steps_given else 1000
+    out = {}
+    for name, wl in (("periodic", W.constrictions()), ("open", W.constrictions(open_ends=True))):
+        stream = torch.cuda.Stream()
+        lat = lbm.lattice_from_workload(wl, storage)
+        lat.set_stream(stream.cuda_stream)
+        ms = _timed_steps(lat, stream, steps, args.warmup)
+        m = lat.reduce()
+        out[name] = {"MLUPS": round(lat.fluid_nodes * steps / (ms * 1e-3) / 1e6, 1),
+                     "ms_per_step": round(ms / steps, 4), "tile": list(lat.get_tile()),
+                     "mass1": float(m[0]), "mass2": float(m[1]), "max_u": float(m[4]),
+                     "nonfinite": int(m[7])}
+        lat.close()
+        print(f"[open] {name} {out[name]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "open vs periodic constriction channel MLUPS",
+                      "workload": f"constrictions 16384x2048, {args.storage} storage, {steps} steps; open: Zou-He "
+                                  "inlet (Poiseuille, peak 0.01) + outflow", "storage": args.storage,
+                      "runs": out, "open_over_periodic": round(out["open"]["MLUPS"] / out["periodic"]["MLUPS"], 4)}),
+          flush=True)
+
+
+def cocurrent_flow(args):
+    """Co-current two-layer flow between walls (Sec. 3.1): Couette (walls
+    sliding at -+0.005) and Poiseuille (body force density 1e-6 on each
+    component), 50x100 fluid rows, nu = 0.17, 10000 steps, FP64 and FP32.
+    Reports the velocity-profile error against the analytic profiles
+    (Couette: linear through the wall planes; Poiseuille: the parabola of
+    the total force density and the mean total density) relative to the
+    profile's peak, and the FP32 error against FP64."""
+    steps = args.steps if args.steps_given else 10000
+    rows = []
+    for flow in ("couette", "poiseuille"):
+        for G_ads in (-0.2, 0.0, 0.2):
+            wl = W.cocurrent(flow, G_ads=G_ads)
+            prof = {}
+            for name, st in (("f64", lbm.F64), ("f32", lbm.F32)):
+                g = lbm.lattice_from_workload(wl, st)
+                g.step(steps)
+                r1, r2, ux, _ = g.get_fields()
+                prof[name] = (ux[1:-1].mean(axis=1), (r1 + r2)[1:-1].mean())
+                g.close()
+            y = np.arange(1, wl.ny - 1) - (wl.ny - 1) / 2.0
+            half = (wl.ny - 2) / 2.0
+            if flow == "couette":
+                ua = wl.wall_velocity[2] * y / half
+            else:
+                nu = (wl.tau - 0.5) / 3.0
+                ua = 2.0 * wl.accel[0] / (2.0 * nu * prof["f64"][1]) * (half ** 2 - y ** 2)
+            peak = float(np.max(np.abs(ua)))
+            rows.append({"flow": flow, "G_ads": G_ads,
+                         "err_vs_analytic": round(float(np.max(np.abs(prof["f64"][0] - ua))) / peak, 5),
+                         "f32_vs_f64": float(np.max(np.abs(prof["f32"][0] - prof["f64"][0]))) / peak})
+            print(f"[cocurrent] {rows[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "co-current flow: max velocity-profile error / peak",
+                      "workload": f"50x100 channel, two layers (a = 25), nu = 0.17, {steps} steps", "rows": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,10 +397,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--workload", default="constrictions",
-                    choices=["constrictions", "calibration", "porous", "cylinder", "schemes"],
+                    choices=["constrictions", "calibration", "porous", "cylinder", "schemes", "open",
+                             "cocurrent"],
                     help="constrictions: the 16384x2048 channel (default); calibration: the 512-run batch; "
                          "porous: the storage precision study; cylinder: the contact-angle sweep per storage; "
-                         "schemes: original against improved adhesion")
+                         "schemes: original against improved adhesion; open: the channel with an inlet and "
+                         "an outflow against the periodic one; cocurrent: Couette and Poiseuille layers")
     ap.add_argument("--record-every", type=int, default=1000, help="porous: recording interval")
     ap.add_argument("--full", action="store_true", help="calibration: run the configured 10000 steps and "
                     "report contact angles")
@@ -358,6 +439,12 @@ def main():
         return
     if args.workload == "schemes":
         scheme_comparison(args)
+        return
+    if args.workload == "open":
+        open_channel(args)
+        return
+    if args.workload == "cocurrent":
+        cocurrent_flow(args)
         return
 
     import torch  # device streams and events only

@@ -68,6 +68,18 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
  *   VEL_LITERAL      u^eq = sum_k j_k / sum_k rho_k (Eq. 4-5 without the
  *                    half-force shift of Guo's scheme);
  *   FORCE_DENSITY    body force g_k per unit volume instead of rho_k g_k.
+ * INLET and OUTFLOW open the x edges (x must not be periodic; EINVAL
+ * otherwise), as in the confined-droplet set-up of Sec. 3.3:
+ *   INLET    Zou-He velocity inlet at x = 0: the populations entering from
+ *            x = -1 are rebuilt so that each component has the row's
+ *            velocity (lbm_set_inlet_velocity);
+ *   OUTFLOW  zero-gradient outflow at x = nx - 1: the populations entering
+ *            from x = nx are those the upstream neighbour receives, i.e.
+ *            pulled from (nx - 1, y - e_iy); bounce-back if that is solid.
+ *   On the E8 stencil (Sec. 2.4) a first-layer position beyond an open
+ *   edge reads its ghost, the node of the same row clamped into the domain
+ *   (zero when that is solid), and a second-layer one takes the Table 1
+ *   copy; the solid switch s of Eq. 9 there is the ghost's.
  * ROUND_STOCHASTIC (F16 and BF16 storage only; ignored otherwise) rounds the
  * stored deviation up or down with probability proportional to the
  * distance, from a counter-based hash of (node, component, direction,
@@ -82,7 +94,9 @@ enum {
     LBM_WALLPSI_SELF = 16,
     LBM_VEL_LITERAL = 32,
     LBM_FORCE_DENSITY = 64,
-    LBM_ROUND_STOCHASTIC = 128
+    LBM_ROUND_STOCHASTIC = 128,
+    LBM_INLET = 256,
+    LBM_OUTFLOW = 512
 };
 
 /* Tile schedule bits for lbm_set_tile. */
@@ -92,7 +106,7 @@ enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2, LBM_SCHED_XCD_SLABS = 4, LBM_SC
 enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
 
 /* Create a context on the current HIP device.  nx, ny >= 5; storage one of
- * LBM_F64..LBM_BF16; flags a combination of LBM_PERIODIC_X..LBM_FORCE_DENSITY.
+ * LBM_F64..LBM_BF16; flags a combination of LBM_PERIODIC_X..LBM_OUTFLOW.
  * Allocates two population buffers of 18*nx*ny elements (ping-pong).
  * Errors: EINVAL (sizes, storage, flags), ENOMEM, EDEVICE (no gfx950 GPU). */
 int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags);
@@ -115,12 +129,27 @@ int lbm_set_adhesion(lbm_ctx *c, double G_w1, double G_w2, double delta);
 /* Body acceleration g_k of each component (force rho_k g_k, Sec. 3.1). */
 int lbm_set_body_accel(lbm_ctx *c, double g1x, double g1y, double g2x, double g2y);
 
+/* Sliding walls (the Couette set-up of Sec. 3.1): solid nodes, and
+ * positions outside a non-periodic y edge, in rows y < ny/2 move with
+ * (ubx, uby), the others with (utx, uty).  A bounce-back link from a moving
+ * wall gains 6 w_i rho*_k (e_i . u_w) (Ladd's momentum term), rho*_k being
+ * the node's own post-collision density.  All zero (the default): resting
+ * walls.  EINVAL on a non-finite value. */
+int lbm_set_wall_velocity(lbm_ctx *c, double ubx, double uby, double utx, double uty);
+
+/* Inlet velocity of each row (ux, uy: ny FP64 each, copied), used with
+ * LBM_INLET, e.g. the Poiseuille profile u_x = 4 U_m eta (1 - eta) of
+ * Sec. 3.3.  Default zero.  EINVAL if a value is non-finite or ux >= 1. */
+int lbm_set_inlet_velocity(lbm_ctx *c, const double *ux, const double *uy);
+
 /* Initial densities (ny*nx each, FP64): f_i = w_i rho_k, u = 0, t = 0.
  * Solid entries are ignored.  EINVAL on a non-finite fluid density. */
 int lbm_init_fields(lbm_ctx *c, const double *rho1, const double *rho2);
 
 /* Pre-collision populations f(x, t) as [2][9][ny][nx] FP64; solid entries
- * ignored on input, returned as 0.  set_populations resets t to 0. */
+ * ignored on input, returned as 0.  set_populations resets t to 0.  The
+ * state set by init_fields or set_populations is taken as given: the open
+ * and moving boundary conditions act from the first step's streaming on. */
 int lbm_set_populations(lbm_ctx *c, const double *f);
 int lbm_get_populations(lbm_ctx *c, double *f);
 
@@ -216,8 +245,9 @@ int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched);
 int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows, unsigned *sched);
 int lbm_autotune(lbm_ctx *c, int steps);
 
-/* Checkpoint: populations, time, parameters.  EIO on file errors; load
- * requires a context of the same size, storage and flags. */
+/* Checkpoint: populations, time, parameters, wall and inlet velocities.
+ * EIO on file errors; load requires a context of the same size, storage
+ * and flags. */
 int lbm_save(lbm_ctx *c, const char *path);
 int lbm_load(lbm_ctx *c, const char *path);
 

@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 OK, EINVAL, ESTATE, ENOMEM, EUNSTABLE = 0, -1, -2, -3, -5
 PERIODIC_X, PERIODIC_Y = 1, 2
 SCHEME_ORIGINAL, E8_COPY_OFF, WALLPSI_SELF, VEL_LITERAL, FORCE_DENSITY = 4, 8, 16, 32, 64
+INLET, OUTFLOW = 256, 512
 
 
 def build(force: bool = True) -> str:
@@ -53,6 +54,8 @@ def lib():
             "oracle_set_params": (I, [P, D, D, D]),
             "oracle_set_adhesion": (I, [P, D, D, D]),
             "oracle_set_body_accel": (I, [P, D, D, D, D]),
+            "oracle_set_wall_velocity": (I, [P, D, D, D, D]),
+            "oracle_set_inlet_velocity": (I, [P, P, P]),
             "oracle_init_fields": (I, [P, P, P]),
             "oracle_set_populations": (I, [P, P]),
             "oracle_get_populations": (I, [P, P]),
@@ -129,6 +132,14 @@ class Oracle:
 
     def set_body_accel(self, g1x, g1y, g2x, g2y):
         self._chk(self._L.oracle_set_body_accel(self.h, g1x, g1y, g2x, g2y))
+
+    def set_wall_velocity(self, ubx, uby, utx, uty):
+        self._chk(self._L.oracle_set_wall_velocity(self.h, ubx, uby, utx, uty))
+
+    def set_inlet_velocity(self, ux, uy):
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(ux, dtype=np.float64), (self.ny,)))
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(uy, dtype=np.float64), (self.ny,)))
+        self._chk(self._L.oracle_set_inlet_velocity(self.h, _ptr(a), _ptr(b)))
 
     def init_fields(self, rho1, rho2):
         r1 = np.ascontiguousarray(rho1, dtype=np.float64).reshape(self.shape)

@@ -14,7 +14,9 @@
  *   4. adhesion with the local parameter G(x)                   (Eq. 9-11)
  *   5. body force, u^eq (Guo half-force shift)                  (Eq. 5, Sec. 3.1)
  *   6. equilibrium, forcing term, BGK collision                 (Eq. 1, 2, 6, 7)
- *   7. streaming with halfway bounce-back at unavailable links  (Eq. 1 LHS, Sec. 3.2, 3.5)
+ *   7. streaming with halfway bounce-back at unavailable links  (Eq. 1 LHS, Sec. 3.2, 3.5),
+ *      optionally from moving walls (Sec. 3.1), with a Zou-He velocity
+ *      inlet and a zero-gradient outflow (Sec. 3.3)
  */
 #include "lbm_oracle.h"
 
@@ -89,6 +91,9 @@ struct oracle_ctx {
     double *rho;   /* [2][n] */
     double Gc, Gw1, Gw2, delta, tau;
     double acc[2][2];
+    double uw[2][2];  /* wall velocity: [0] rows y < ny/2, [1] the others */
+    int moving;       /* any wall velocity nonzero */
+    double *inlet;    /* [2][ny] inlet velocity per row */
     int have_geom, have_params, have_fields;
     long t;
     char err[256];
@@ -133,12 +138,36 @@ static int available(const oracle_ctx *c, int x, int y)
     return id >= 0 && !c->solid[id];
 }
 
+/* A position beyond an open x edge (the inlet left of x = 0, the outflow
+ * right of x = nx - 1): its ghost is the node of the same row clamped into
+ * the domain.  Returns the ghost's node id, -1 when the ghost is solid or
+ * outside, or -2 when the position does not lie beyond an open edge. */
+static int open_ghost(const oracle_ctx *c, int x, int y)
+{
+    int cx;
+    if (x < 0 && (c->flags & ORC_INLET)) cx = 0;
+    else if (x >= c->nx && (c->flags & ORC_OUTFLOW)) cx = c->nx - 1;
+    else return -2;
+    return available(c, cx, y) ? node_at(c, cx, y) : -1;
+}
+
+/* s(P) of Eq. 9: 1 on a solid position or one outside a closed edge; a
+ * position beyond an open edge takes its ghost's value. */
+static double solid_switch(const oracle_ctx *c, int x, int y)
+{
+    if (available(c, x, y)) return 0.0;
+    int g = open_ghost(c, x, y);
+    if (g == -2) return 1.0;
+    return g >= 0 ? 0.0 : 1.0;
+}
+
 int oracle_create(oracle_ctx **out, int nx, int ny, unsigned flags)
 {
     if (!out) return ORC_EINVAL;
     *out = NULL;
     if (nx < 5 || ny < 5) return ORC_EINVAL;
-    if (flags & ~127u) return ORC_EINVAL;
+    if (flags & ~(127u | ORC_INLET | ORC_OUTFLOW)) return ORC_EINVAL;
+    if ((flags & (ORC_INLET | ORC_OUTFLOW)) && (flags & ORC_PERIODIC_X)) return ORC_EINVAL;
     oracle_ctx *c = (oracle_ctx *)calloc(1, sizeof *c);
     if (!c) return ORC_ENOMEM;
     c->nx = nx;
@@ -149,7 +178,8 @@ int oracle_create(oracle_ctx **out, int nx, int ny, unsigned flags)
     c->f = (double *)calloc((size_t)c->n * 18, sizeof(double));
     c->fpost = (double *)calloc((size_t)c->n * 18, sizeof(double));
     c->rho = (double *)calloc((size_t)c->n * 2, sizeof(double));
-    if (!c->solid || !c->f || !c->fpost || !c->rho) {
+    c->inlet = (double *)calloc((size_t)ny * 2, sizeof(double));
+    if (!c->solid || !c->f || !c->fpost || !c->rho || !c->inlet) {
         oracle_destroy(c);
         return ORC_ENOMEM;
     }
@@ -165,6 +195,7 @@ void oracle_destroy(oracle_ctx *c)
     free(c->f);
     free(c->fpost);
     free(c->rho);
+    free(c->inlet);
     free(c);
 }
 
@@ -229,6 +260,31 @@ int oracle_set_body_accel(oracle_ctx *c, double g1x, double g1y, double g2x, dou
     c->acc[0][1] = g1y;
     c->acc[1][0] = g2x;
     c->acc[1][1] = g2y;
+    return ORC_OK;
+}
+
+int oracle_set_wall_velocity(oracle_ctx *c, double ubx, double uby, double utx, double uty)
+{
+    if (!c) return ORC_EINVAL;
+    if (!isfinite(ubx) || !isfinite(uby) || !isfinite(utx) || !isfinite(uty))
+        return fail(c, ORC_EINVAL, "non-finite wall velocity");
+    c->uw[0][0] = ubx;
+    c->uw[0][1] = uby;
+    c->uw[1][0] = utx;
+    c->uw[1][1] = uty;
+    c->moving = ubx != 0.0 || uby != 0.0 || utx != 0.0 || uty != 0.0;
+    return ORC_OK;
+}
+
+int oracle_set_inlet_velocity(oracle_ctx *c, const double *ux, const double *uy)
+{
+    if (!c || !ux || !uy) return ORC_EINVAL;
+    for (int y = 0; y < c->ny; ++y) {
+        if (!isfinite(ux[y]) || !isfinite(uy[y]) || !(ux[y] < 1.0))
+            return fail(c, ORC_EINVAL, "inlet velocity must be finite with u_x < 1");
+        c->inlet[y] = ux[y];
+        c->inlet[c->ny + y] = uy[y];
+    }
     return ORC_OK;
 }
 
@@ -345,9 +401,11 @@ void oracle_e8(int ex[24], int ey[24], double W[24], int copy_from[24])
 
 /* Stencil position n as seen from node (x, y): the node id that feeds it
  * after the unavailable-position rules, or -1 for the value zero.
- *   first layer : available ? neighbour : (WALLPSI_SELF ? self : zero)
+ *   first layer : available ? neighbour : beyond an open edge with a fluid
+ *                 ghost ? ghost : (WALLPSI_SELF ? self : zero)
  *   second layer: available ? neighbour : (COPY_OFF ? zero : value of m(n))
- * (Sec. 2.4 and Table 1 for the copy; Eq. 8-9 for what a wall contributes.) */
+ * (Sec. 2.4 and Table 1 for the copy, which the paper applies at velocity
+ * boundaries as at walls; Eq. 8-9 for what a wall contributes.) */
 static void resolve_sources(const oracle_ctx *c, int x, int y, int src[24])
 {
     int self = y * c->nx + x;
@@ -358,10 +416,13 @@ static void resolve_sources(const oracle_ctx *c, int x, int y, int src[24])
             continue;
         }
         int m = table1_source(n);
-        if (m < 0)
-            src[n] = (c->flags & ORC_WALLPSI_SELF) ? self : -1;
-        else
+        if (m < 0) {
+            int g = open_ghost(c, px, py);
+            if (g >= 0) src[n] = g;
+            else src[n] = (c->flags & ORC_WALLPSI_SELF) ? self : -1;
+        } else {
             src[n] = (c->flags & ORC_E8_COPY_OFF) ? -1 : src[m];
+        }
     }
 }
 
@@ -374,8 +435,8 @@ static void adhesion_vector(const oracle_ctx *c, int x, int y, double S[2])
     for (int g = 0; g < 6; ++g)
         for (int h = 0; h < 2; ++h) {
             int n = 4 * g + h, o = n + 2; /* o is the position opposite n */
-            double sn = available(c, x + SX[n], y + SY[n]) ? 0.0 : 1.0;
-            double so = available(c, x + SX[o], y + SY[o]) ? 0.0 : 1.0;
+            double sn = solid_switch(c, x + SX[n], y + SY[n]);
+            double so = solid_switch(c, x + SX[o], y + SY[o]);
             double W = e8_weight(SX[n] * SX[n] + SY[n] * SY[n]);
             S[0] += W * SX[n] * (sn - so);
             S[1] += W * SY[n] * (sn - so);
@@ -507,6 +568,53 @@ static int ready(oracle_ctx *c)
     return ORC_OK;
 }
 
+/* Streaming into fluid node (x, y), component k.  The source is x - e_i,
+ * except right of the outflow, where it is (x, y - e_iy): the node whose
+ * population the upstream neighbour at x - 1 receives (zero normal
+ * gradient).  Then
+ *   f_i(x, t+1) = f*_i(source, t) when the source is available;
+ *   a source left of the inlet: Zou-He unknown (below);
+ *   otherwise halfway bounce-back f*_opp(i)(x, t), plus 6 w_i rho*_k
+ *     (e_i . u_w) when the wall at the source moves (Ladd), rho*_k being
+ *     the node's own post-collision density sum_j f*_j(x, t).
+ * Zou-He at the inlet (west edge, velocity (U, V) of the row): with the
+ * known populations, rho = [f0 + f2 + f4 + 2 (f3 + f6 + f7)] / (1 - U),
+ * f1 = f3 + 2/3 rho U, f5 = f7 - (f2 - f4)/2 + rho U/6 + rho V/2,
+ * f8 = f6 + (f2 - f4)/2 + rho U/6 - rho V/2. */
+static void stream_node(oracle_ctx *c, int k, int x, int y)
+{
+    int id = y * c->nx + x;
+    double f[9];
+    int unknown = 0;
+    double rpost = 0.0;
+    if (c->moving)
+        for (int j = 0; j < 9; ++j) rpost += FP_AT(c, k, j, id);
+    for (int i = 0; i < 9; ++i) {
+        int sx = x - QX[i], sy = y - QY[i];
+        if (sx >= c->nx && (c->flags & ORC_OUTFLOW)) sx = x;
+        if (available(c, sx, sy)) {
+            f[i] = FP_AT(c, k, i, node_at(c, sx, sy));
+        } else if (sx < 0 && (c->flags & ORC_INLET)) {
+            f[i] = 0.0;
+            unknown = 1;
+        } else {
+            f[i] = FP_AT(c, k, QOPP[i], id);
+            if (c->moving) {
+                const double *u = c->uw[sy < c->ny / 2 ? 0 : 1];
+                f[i] += 6.0 * QW[i] * rpost * (QX[i] * u[0] + QY[i] * u[1]);
+            }
+        }
+    }
+    if (unknown) {
+        double U = c->inlet[y], V = c->inlet[c->ny + y];
+        double rho = (((f[0] + f[2]) + f[4]) + 2.0 * ((f[3] + f[6]) + f[7])) / (1.0 - U);
+        f[1] = f[3] + (2.0 / 3.0) * rho * U;
+        f[5] = ((f[7] - 0.5 * (f[2] - f[4])) + (1.0 / 6.0) * rho * U) + 0.5 * rho * V;
+        f[8] = ((f[6] + 0.5 * (f[2] - f[4])) + (1.0 / 6.0) * rho * U) - 0.5 * rho * V;
+    }
+    for (int i = 0; i < 9; ++i) F_AT(c, k, i, id) = f[i];
+}
+
 int oracle_step(oracle_ctx *c, int nsteps)
 {
     int rc = ready(c);
@@ -533,21 +641,13 @@ int oracle_step(oracle_ctx *c, int nsteps)
                     }
                 }
             }
-        /* streaming: f_i(x, t+1) = f*_i(x - e_i, t), or the reflected
-         * population f*_opp(i)(x, t) when x - e_i is unavailable */
+        /* streaming */
 #pragma omp parallel for schedule(static)
         for (int y = 0; y < c->ny; ++y)
             for (int x = 0; x < c->nx; ++x) {
                 int id = y * c->nx + x;
                 if (c->solid[id]) continue;
-                for (int k = 0; k < 2; ++k)
-                    for (int i = 0; i < 9; ++i) {
-                        int sx = x - QX[i], sy = y - QY[i];
-                        if (available(c, sx, sy))
-                            F_AT(c, k, i, id) = FP_AT(c, k, i, node_at(c, sx, sy));
-                        else
-                            F_AT(c, k, i, id) = FP_AT(c, k, QOPP[i], id);
-                    }
+                for (int k = 0; k < 2; ++k) stream_node(c, k, x, y);
             }
         c->t += 1;
     }

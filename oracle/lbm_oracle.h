@@ -48,7 +48,9 @@ enum {
     ORC_E8_COPY_OFF = 8,       /* unavailable second layer -> 0, no copy    */
     ORC_WALLPSI_SELF = 16,     /* unavailable first layer -> psi(x), not 0  */
     ORC_VEL_LITERAL = 32,      /* u^eq = sum j / sum rho (Eq. 4-5 literal)  */
-    ORC_FORCE_DENSITY = 64     /* body force = g_k, not rho_k g_k           */
+    ORC_FORCE_DENSITY = 64,    /* body force = g_k, not rho_k g_k           */
+    ORC_INLET = 256,           /* Zou-He velocity inlet at x = 0 (Sec. 3.3) */
+    ORC_OUTFLOW = 512          /* zero-gradient outflow at x = nx - 1       */
 };
 
 typedef struct oracle_ctx oracle_ctx;
@@ -63,6 +65,14 @@ int oracle_set_params(oracle_ctx *c, double G_c, double G_ads, double tau);
 /* paper-native adhesion parameters of Eq. 9-12 */
 int oracle_set_adhesion(oracle_ctx *c, double G_w1, double G_w2, double delta);
 int oracle_set_body_accel(oracle_ctx *c, double g1x, double g1y, double g2x, double g2y);
+/* Open and moving boundaries (Sec. 3.1 sliding walls, Sec. 3.3 inlet and
+ * outflow).  Solid nodes (and positions outside a non-periodic y edge) in
+ * rows y < ny/2 move with (ubx, uby), the others with (utx, uty); a
+ * bounce-back link from a moving wall gains 6 w_i rho*_k (e_i . u_w)
+ * (Ladd), rho*_k being the node's own post-collision density.  The inlet
+ * velocity of row y is (ux[y], uy[y]) (arrays of ny, copied). */
+int oracle_set_wall_velocity(oracle_ctx *c, double ubx, double uby, double utx, double uty);
+int oracle_set_inlet_velocity(oracle_ctx *c, const double *ux, const double *uy);
 /* f_i = w_i rho_k (u = 0) on fluid nodes */
 int oracle_init_fields(oracle_ctx *c, const double *rho1, const double *rho2);
 int oracle_set_populations(oracle_ctx *c, const double *f);

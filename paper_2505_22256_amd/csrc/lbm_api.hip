@@ -36,6 +36,13 @@ struct lbm_ctx {
     double Gc = 0, Gw1 = 0, Gw2 = 0, delta = 0.8, tau = 1.0;
     double acc[2][2] = {{0, 0}, {0, 0}};
     double rho0[2] = {0, 0};
+    double uw[2][2] = {{0, 0}, {0, 0}};  // wall velocity: rows y < ny/2, the others
+    std::vector<double> inlet;           // [2][ny] inlet velocity (LBM_INLET)
+    double *d_inlet = nullptr;
+    // the populations were just set (init_fields, set_populations): the
+    // next pull reproduces them as given, without the open or moving
+    // boundary conditions
+    bool fresh = false;
     bool have_geom = false, have_params = false, have_fields = false;
     long t = 0;
     int block = 256, seg_rows = 0;
@@ -96,6 +103,11 @@ int ensure_partials(lbm_ctx *c, size_t nparts)
     return LBM_OK;
 }
 
+bool moving_walls(const lbm_ctx *c)
+{
+    return c->uw[0][0] != 0.0 || c->uw[0][1] != 0.0 || c->uw[1][0] != 0.0 || c->uw[1][1] != 0.0;
+}
+
 template <class C>
 KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int seg_rows, int halo = 2)
 {
@@ -115,7 +127,20 @@ KParams<C> make_params(const lbm_ctx *c, const void *A, void *B, int block, int 
     p.tick = (unsigned)c->t;
     p.N = c->N;
     fill_physics<C>(p, c->flags, c->Gc, c->Gw1, c->Gw2, c->delta, c->tau, c->acc, c->rho0, c->storage != LBM_F64);
+    for (int w = 0; w < 2; ++w)
+        for (int a = 0; a < 2; ++a) p.uw[w][a] = (C)c->uw[w][a];
+    p.moving = moving_walls(c) ? 1 : 0;
+    p.plain = c->fresh ? 1 : 0;
+    p.inlet = c->d_inlet;
     return p;
+}
+
+// Open or moving boundaries are on.  Right after the populations were set
+// the first step must pull them as given while the second applies the
+// boundary conditions, so that step runs alone.
+bool boundary_steps(const lbm_ctx *c)
+{
+    return (c->flags & (LBM_INLET | LBM_OUTFLOW)) || moving_walls(c);
 }
 
 int grid_of(int strips, int segs) { return ((strips * segs + 7) / 8) * 8; }
@@ -172,8 +197,9 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
     p.tab_link = link;
     p.tab_nw = nw;
     p.tab_src = src;
+    if (pass == P_TABLES) p.plain = 1;  // link bits: plain unavailability of each source
     const bool sr = (S == ST_F16 || S == ST_BF16) && (c->flags & LBM_ROUND_STOCHASTIC);
-    const hipError_t e = launch_pass<S>(p, pass, block, sr, c->stream);
+    const hipError_t e = launch_pass<S>(p, pass, block, sr, boundary_steps(c), c->stream);
     if (e != hipSuccess) return set_err(c, LBM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
@@ -276,6 +302,7 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
     if (nx < 5 || ny < 5 || (long long)nx * ny > (1LL << 30)) return LBM_EINVAL;
     if (storage < LBM_F64 || storage > LBM_BF16) return LBM_EINVAL;
     if (flags & ~(unsigned)FL_ALL) return LBM_EINVAL;
+    if ((flags & (LBM_INLET | LBM_OUTFLOW)) && (flags & LBM_PERIODIC_X)) return LBM_EINVAL;
     // one component's 9 direction arrays are addressed through a 32-bit range
     if ((long long)nx * ny * 9 * (long long)elem_size(storage) >= (1LL << 32)) return LBM_EINVAL;
     int ndev = 0;
@@ -303,10 +330,16 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
     }
     c->stream = c->own_stream;
     bool ok = hipMalloc(&c->buf[0], bytes) == hipSuccess && hipMalloc(&c->buf[1], bytes) == hipSuccess &&
-              hipMalloc(&c->d_solid, (size_t)c->N) == hipSuccess && hipMalloc(&c->d_out, 32 * sizeof(double)) == hipSuccess;
+              hipMalloc(&c->d_solid, (size_t)c->N) == hipSuccess && hipMalloc(&c->d_out, 32 * sizeof(double)) == hipSuccess &&
+              hipMalloc(&c->d_inlet, (size_t)ny * 2 * sizeof(double)) == hipSuccess;
     if (!ok) {
         lbm_destroy(c);
         return LBM_ENOMEM;
+    }
+    c->inlet.assign((size_t)ny * 2, 0.0);
+    if (hipMemcpy(c->d_inlet, c->inlet.data(), (size_t)ny * 2 * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        lbm_destroy(c);
+        return LBM_EDEVICE;
     }
     c->solid.assign((size_t)c->N, 0);
     // measured defaults on the 16384 x 2048 channel: FP32 fuses two steps
@@ -337,6 +370,7 @@ void lbm_destroy(lbm_ctx *c)
     if (c->d_tmp) (void)hipFree(c->d_tmp);
     if (c->d_partials) (void)hipFree(c->d_partials);
     if (c->d_out) (void)hipFree(c->d_out);
+    if (c->d_inlet) (void)hipFree(c->d_inlet);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
@@ -410,6 +444,33 @@ int lbm_set_body_accel(lbm_ctx *c, double g1x, double g1y, double g2x, double g2
     return LBM_OK;
 }
 
+int lbm_set_wall_velocity(lbm_ctx *c, double ubx, double uby, double utx, double uty)
+{
+    if (!c) return LBM_EINVAL;
+    if (!std::isfinite(ubx) || !std::isfinite(uby) || !std::isfinite(utx) || !std::isfinite(uty))
+        return set_err(c, LBM_EINVAL, "non-finite wall velocity");
+    c->uw[0][0] = ubx;
+    c->uw[0][1] = uby;
+    c->uw[1][0] = utx;
+    c->uw[1][1] = uty;
+    return LBM_OK;
+}
+
+int lbm_set_inlet_velocity(lbm_ctx *c, const double *ux, const double *uy)
+{
+    if (!c || !ux || !uy) return LBM_EINVAL;
+    for (int y = 0; y < c->ny; ++y)
+        if (!std::isfinite(ux[y]) || !std::isfinite(uy[y]) || !(ux[y] < 1.0))
+            return set_err(c, LBM_EINVAL, "inlet velocity must be finite with u_x < 1");
+    for (int y = 0; y < c->ny; ++y) {
+        c->inlet[(size_t)y] = ux[y];
+        c->inlet[(size_t)(c->ny + y)] = uy[y];
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->d_inlet, c->inlet.data(), (size_t)c->ny * 2 * sizeof(double), hipMemcpyHostToDevice));
+    return LBM_OK;
+}
+
 int lbm_init_fields(lbm_ctx *c, const double *rho1, const double *rho2)
 {
     if (!c || !rho1 || !rho2) return LBM_EINVAL;
@@ -435,6 +496,7 @@ int lbm_init_fields(lbm_ctx *c, const double *rho1, const double *rho2)
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_fields = true;
+    c->fresh = true;
     c->t = 0;
     c->diag_t = -1;
     return LBM_OK;
@@ -466,6 +528,7 @@ int lbm_set_populations(lbm_ctx *c, const double *f)
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_fields = true;
+    c->fresh = true;
     c->t = 0;
     return LBM_OK;
 }
@@ -512,7 +575,8 @@ int lbm_step(lbm_ctx *c, int n)
     for (int s = 0; s < n; ++s) {
         const bool diag_now = c->diag_every > 0 && c->t % c->diag_every == 0;
         const bool diag_next = c->diag_every > 0 && (c->t + 1) % c->diag_every == 0;
-        if (two && !(diag_now && diag_next) && n - s >= 2) {
+        const bool alone = c->fresh && boundary_steps(c);
+        if (two && !alone && !(diag_now && diag_next) && n - s >= 2) {
             // two fused steps, recording the diagnostics of whichever of
             // them is due
             const Pass pass = diag_now ? P_STEP2_RED1 : diag_next ? P_STEP2_RED2 : P_STEP2;
@@ -527,6 +591,7 @@ int lbm_step(lbm_ctx *c, int n)
             }
             c->cur ^= 1;
             c->t += 2;
+            c->fresh = false;
             ++s;
             continue;
         }
@@ -543,6 +608,7 @@ int lbm_step(lbm_ctx *c, int n)
         }
         c->cur ^= 1;
         c->t += 1;
+        c->fresh = false;
     }
     return LBM_OK;
 }
@@ -722,6 +788,7 @@ int lbm_autotune(lbm_ctx *c, int steps)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&ev0);
     if (e == hipSuccess) e = hipEventCreate(&ev1);
+    const bool fresh0 = c->fresh;
     const int blocks[3] = {64, 128, 256};
     const int rows[10] = {0, 8, 16, 24, 32, 48, 64, 128, 256, 512};
     const int cur_b = c->block, cur_r = c->seg_rows;
@@ -773,6 +840,7 @@ int lbm_autotune(lbm_ctx *c, int steps)
     (void)hipFree(backup);
     c->cur = cur0;
     c->t = t0;
+    c->fresh = fresh0;
     c->diag_t = diag_t0;
     c->block = best_b;
     c->seg_rows = best_r;
@@ -790,6 +858,12 @@ struct CkptHeader {
     long long t;
     double Gc, Gw1, Gw2, delta, tau, acc[4], rho0[2];
 };
+// version 2 appends this block (and, after the populations, the inlet
+// velocity [2][ny] FP64)
+struct CkptBoundary {
+    int fresh, pad;
+    double uw[4];
+};
 
 int lbm_save(lbm_ctx *c, const char *path)
 {
@@ -803,7 +877,7 @@ int lbm_save(lbm_ctx *c, const char *path)
     CkptHeader h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, "LBM2CPK", 8);
-    h.version = 1;
+    h.version = 2;
     h.nx = c->nx;
     h.ny = c->ny;
     h.storage = c->storage;
@@ -820,10 +894,19 @@ int lbm_save(lbm_ctx *c, const char *path)
     h.acc[3] = c->acc[1][1];
     h.rho0[0] = c->rho0[0];
     h.rho0[1] = c->rho0[1];
+    CkptBoundary hb;
+    std::memset(&hb, 0, sizeof hb);
+    hb.fresh = c->fresh ? 1 : 0;
+    hb.uw[0] = c->uw[0][0];
+    hb.uw[1] = c->uw[0][1];
+    hb.uw[2] = c->uw[1][0];
+    hb.uw[3] = c->uw[1][1];
     FILE *fp = std::fopen(path, "wb");
     if (!fp) return set_err(c, LBM_EIO, "cannot open %s", path);
-    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(c->solid.data(), 1, (size_t)c->N, fp) == (size_t)c->N &&
-              std::fwrite(host.data(), 1, bytes, fp) == bytes;
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(&hb, sizeof hb, 1, fp) == 1 &&
+              std::fwrite(c->solid.data(), 1, (size_t)c->N, fp) == (size_t)c->N &&
+              std::fwrite(host.data(), 1, bytes, fp) == bytes &&
+              std::fwrite(c->inlet.data(), sizeof(double), c->inlet.size(), fp) == c->inlet.size();
     ok = (std::fclose(fp) == 0) && ok;
     if (!ok) return set_err(c, LBM_EIO, "write to %s failed", path);
     return LBM_OK;
@@ -839,12 +922,17 @@ int lbm_load(lbm_ctx *c, const char *path)
     std::vector<uint8_t> sol((size_t)c->N);
     std::vector<char> host(bytes);
     bool ok = std::fread(&h, sizeof h, 1, fp) == 1;
-    if (ok && (std::memcmp(h.magic, "LBM2CPK", 8) != 0 || h.version != 1 || h.nx != c->nx || h.ny != c->ny ||
-               h.storage != c->storage || h.flags != c->flags)) {
+    if (ok && (std::memcmp(h.magic, "LBM2CPK", 8) != 0 || (h.version != 1 && h.version != 2) || h.nx != c->nx ||
+               h.ny != c->ny || h.storage != c->storage || h.flags != c->flags)) {
         std::fclose(fp);
         return set_err(c, LBM_EINVAL, "checkpoint does not match this context");
     }
+    CkptBoundary hb;
+    std::memset(&hb, 0, sizeof hb);  // version 1: no open or moving boundaries
+    std::vector<double> inl((size_t)c->ny * 2, 0.0);
+    if (ok && h.version == 2) ok = std::fread(&hb, sizeof hb, 1, fp) == 1;
     ok = ok && std::fread(sol.data(), 1, (size_t)c->N, fp) == (size_t)c->N && std::fread(host.data(), 1, bytes, fp) == bytes;
+    if (ok && h.version == 2) ok = std::fread(inl.data(), sizeof(double), inl.size(), fp) == inl.size();
     std::fclose(fp);
     if (!ok) return set_err(c, LBM_EIO, "short read from %s", path);
     int rc = lbm_set_geometry(c, sol.data());
@@ -860,12 +948,19 @@ int lbm_load(lbm_ctx *c, const char *path)
     c->acc[1][1] = h.acc[3];
     c->rho0[0] = h.rho0[0];
     c->rho0[1] = h.rho0[1];
+    c->uw[0][0] = hb.uw[0];
+    c->uw[0][1] = hb.uw[1];
+    c->uw[1][0] = hb.uw[2];
+    c->uw[1][1] = hb.uw[3];
     c->have_params = true;
+    rc = lbm_set_inlet_velocity(c, inl.data(), inl.data() + c->ny);
+    if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(c->buf[0], host.data(), bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->buf[1], 0xff, bytes, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cur = 0;
     c->t = (long)h.t;
+    c->fresh = hb.fresh != 0;
     c->have_fields = true;
     return LBM_OK;
 }

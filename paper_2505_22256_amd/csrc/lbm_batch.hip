@@ -354,7 +354,9 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
     for (int r = 0; r < nruns; ++r) {
         const lbm_run_desc &d = runs[r];
         BatchRun &br = b->runs[(size_t)r];
-        if (d.nx < 5 || d.ny < 5 || !d.solid || !d.rho1 || !d.rho2 || (d.flags & ~(unsigned)FL_ALL) || !(d.tau > 0.5) ||
+        // batches run closed, resting walls (no inlet, outflow or sliding wall)
+        if (d.nx < 5 || d.ny < 5 || !d.solid || !d.rho1 || !d.rho2 || (d.flags & ~(unsigned)FL_ALL) ||
+            (d.flags & (LBM_INLET | LBM_OUTFLOW)) || !(d.tau > 0.5) ||
             !std::isfinite(d.tau) || !std::isfinite(d.G_c) || !std::isfinite(d.G_ads) ||
             (d.wall_kind != LBM_WALL_FLAT && d.wall_kind != LBM_WALL_CYLINDER)) {
             delete b;

@@ -26,7 +26,9 @@ enum : unsigned {
     FL_VEL_LITERAL = 32u,
     FL_FORCE_DENSITY = 64u,
     FL_ROUND_STOCHASTIC = 128u,
-    FL_ALL = 255u
+    FL_INLET = 256u,    // Zou-He velocity inlet at x = 0 (Sec. 3.3)
+    FL_OUTFLOW = 512u,  // zero-gradient outflow at x = nx - 1 (Sec. 3.3)
+    FL_ALL = 1023u
 };
 
 // Kernel modes (bit set).
@@ -38,7 +40,8 @@ enum : int {
     M_SR = 16,     // stochastic rounding of FP16 / BF16 stores (compile-time)
     M_LDS = 32,    // first of two fused steps: post-collision values to the LDS ring
     M_TWO = 64,    // kernel advances two steps per launch
-    M_DIAG_FIRST = 128  // two steps: M_REDUCE records the first step (else the second)
+    M_DIAG_FIRST = 128,  // two steps: M_REDUCE records the first step (else the second)
+    M_BND = 256          // open and moving boundaries compiled in (else plain walls only)
 };
 
 // ---------------------------------------------------------------------------
@@ -248,6 +251,15 @@ template <class C> struct KParams {
     C omega_rho0[2];     // omega * rho0_k
     C g[2][2];
     C rho0[2];      // deviation base density per component (zero for FP64)
+    // open and moving boundaries (Sec. 3.1 sliding walls, Sec. 3.3 inlet and
+    // outflow): wall velocity of rows y < ny/2 ([0]) and of the others ([1]);
+    // inlet velocity per row [2][ny]; `plain` pulls without these boundary
+    // conditions (the state right after it was set, which the populations
+    // themselves define)
+    C uw[2][2];
+    int moving;
+    int plain;
+    const double *inlet;
     // mode outputs
     double *out_rho1, *out_rho2, *out_ux, *out_uy;
     double *partials;
@@ -304,6 +316,19 @@ __device__ __forceinline__ Axis make_axis_near(int v, int n, bool periodic)
         a.ok = v >= 0 && v < n;
         a.okm = v - 1 >= 0 && v - 1 < n;
         a.okp = v + 1 >= 0 && v + 1 < n;
+    }
+    return a;
+}
+
+// The column axis of the outflow column pulls the populations that enter
+// from outside (directions 3, 6, 7) from its own column, rows y - e_iy:
+// what the upstream neighbour receives (zero normal gradient).
+template <class P>
+__device__ __forceinline__ Axis open_axis(Axis a, const P &p)
+{
+    if ((p.flags & FL_OUTFLOW) && !p.plain && a.c == p.nx - 1) {
+        a.p = p.nx - 1;
+        a.okp = true;
     }
     return a;
 }

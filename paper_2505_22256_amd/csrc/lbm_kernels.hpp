@@ -119,7 +119,7 @@ template <int S> struct GlobalReload {
 // f_i(x, t), with halfway bounce-back f_i(x, t) = f*_opp(i)(x, t-1) where
 // the source is unavailable (a sentinel or outside the domain), and the
 // densities rho_k = sum_i f_i (Eq. 3) in the definition's summation order.
-template <int S, class Reload>
+template <int S, bool BND, class Reload>
 __device__ __forceinline__ void process_node_src(const KParams<typename Traits<S>::C> &p, const Reload &reload,
                                                  const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
                                                  RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
@@ -146,21 +146,97 @@ __device__ __forceinline__ void process_node_src(const KParams<typename Traits<S
     s1 += p.rho0[0];
     s2 += p.rho0[1];
     st.info = 0;
-    if (__builtin_isnan(s1 + s2)) {
-        // an unavailable source (or a non-finite state): reflect
+    if constexpr (!BND) {
+        if (__builtin_isnan(s1 + s2)) {
+            // an unavailable source (or a non-finite state): reflect
+            int info = 0;
+            s1 = 0;
+            s2 = 0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                int col, row;
+                bool ok;
+                pull_source(i, cx, ry, col, row, ok);
+                if (i > 0 && (!ok || T::sent(q.v[0][i]))) {
+                    info |= 1 << (i - 1);
+                    st.f[0][i] = T::dec(reload(0, opp(i)));
+                    st.f[1][i] = T::dec(reload(1, opp(i)));
+                }
+                s1 += st.f[0][i];
+                s2 += st.f[1][i];
+            }
+            st.info = info;
+            s1 += p.rho0[0];
+            s2 += p.rho0[1];
+        }
+    } else if (__builtin_isnan(s1 + s2)) {
+        // an unavailable source (or a non-finite state): reflect, from a
+        // moving wall with Ladd's momentum term 6 w_i rho*_k (e_i . u_w)
+        // (rho*_k: the node's own post-collision density); a source left of
+        // the inlet is a Zou-He unknown
+        const bool inlet = (p.flags & FL_INLET) && !p.plain && cx.c == 0;
+        const bool moving = p.moving && !p.plain;
+        C rp[2] = {0, 0};
+        if (moving) {
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                rp[0] += T::dec(reload(0, j));
+                rp[1] += T::dec(reload(1, j));
+            }
+            rp[0] += p.rho0[0];
+            rp[1] += p.rho0[1];
+        }
         int info = 0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            int col, row;
+            bool ok;
+            pull_source(i, cx, ry, col, row, ok);
+            if (!ok || T::sent(q.v[0][i])) {
+                info |= 1 << (i - 1);
+                if (inlet && qx(i) == 1) continue;  // rebuilt below
+                st.f[0][i] = T::dec(reload(0, opp(i)));
+                st.f[1][i] = T::dec(reload(1, opp(i)));
+                if (moving) {
+                    // no fused multiply-adds: the same rounding in every
+                    // kernel that inlines this (one or two steps per launch)
+#pragma clang fp contract(off)
+                    const int sy_row = ry.c - qy(i);
+                    const C ux = sy_row < p.ny / 2 ? p.uw[0][0] : p.uw[1][0];
+                    const C uy = sy_row < p.ny / 2 ? p.uw[0][1] : p.uw[1][1];
+                    const C eu = (C)qx(i) * ux + (C)qy(i) * uy;
+                    st.f[0][i] += (C)(6.0 * qw(i)) * rp[0] * eu;
+                    st.f[1][i] += (C)(6.0 * qw(i)) * rp[1] * eu;
+                }
+            }
+        }
+        if (inlet) {
+            // Zou-He on the west edge with the row's velocity (U, V):
+            // rho = [f0 + f2 + f4 + 2 (f3 + f6 + f7)] / (1 - U),
+            // f1 = f3 + 2/3 rho U, f5 = f7 - (f2 - f4)/2 + rho U/6 + rho V/2,
+            // f8 = f6 + (f2 - f4)/2 + rho U/6 - rho V/2 (full populations;
+            // deviations add back w_i rho0)
+#pragma clang fp contract(off)
+            const C U = (C)p.inlet[ry.c], V = (C)p.inlet[p.ny + ry.c];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                C F[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) F[i] = st.f[k][i] + (C)qw(i) * p.rho0[k];
+                const C rho = (((F[0] + F[2]) + F[4]) + (C)2 * ((F[3] + F[6]) + F[7])) / ((C)1 - U);
+                const C d24 = F[2] - F[4];
+                F[1] = F[3] + (C)(2.0 / 3.0) * rho * U;
+                F[5] = ((F[7] - (C)0.5 * d24) + (C)(1.0 / 6.0) * rho * U) + (C)0.5 * rho * V;
+                F[8] = ((F[6] + (C)0.5 * d24) + (C)(1.0 / 6.0) * rho * U) - (C)0.5 * rho * V;
+                st.f[k][1] = F[1] - (C)qw(1) * p.rho0[k];
+                st.f[k][5] = F[5] - (C)qw(5) * p.rho0[k];
+                st.f[k][8] = F[8] - (C)qw(8) * p.rho0[k];
+            }
+        }
         s1 = 0;
         s2 = 0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            int col, row;
-            bool ok;
-            pull_source(i, cx, ry, col, row, ok);
-            if (i > 0 && (!ok || T::sent(q.v[0][i]))) {
-                info |= 1 << (i - 1);
-                st.f[0][i] = T::dec(reload(0, opp(i)));
-                st.f[1][i] = T::dec(reload(1, opp(i)));
-            }
             s1 += st.f[0][i];
             s2 += st.f[1][i];
         }
@@ -172,18 +248,18 @@ __device__ __forceinline__ void process_node_src(const KParams<typename Traits<S
     r2 = s2;
 }
 
-template <int S>
+template <int S, bool BND>
 __device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
                                              const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
                                              RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
                                              typename Traits<S>::C &r2)
 {
     const GlobalReload<S> reload{m, (uint32_t)(ry.c * p.nx + cx.c) * (uint32_t)sizeof(typename Traits<S>::raw_t)};
-    process_node_src<S>(p, reload, cx, ry, valid, q, st, r1, r2);
+    process_node_src<S, BND>(p, reload, cx, ry, valid, q, st, r1, r2);
 }
 
 // Process a prefetched row: node state into `st`, psi into the LDS ring.
-template <int S, int BLOCK, int RS = 8>
+template <int S, int BLOCK, int RS, bool BND>
 __device__ __forceinline__ void process_row(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
                                             const Axis &cx, bool col_ok, int r, const RawRow<S> &q,
                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
@@ -192,7 +268,7 @@ __device__ __forceinline__ void process_row(const KParams<typename Traits<S>::C>
     using C = typename Traits<S>::C;
     const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
     C r1 = 0, r2 = 0;
-    process_node<S>(p, m, cx, ry, col_ok && ry.ok, q, st, r1, r2);
+    process_node<S, BND>(p, m, cx, ry, col_ok && ry.ok, q, st, r1, r2);
     PsiPair<C> ps;
     ps.a = (st.info & 256) ? lds_sentinel<C>() : r1;
     ps.b = (st.info & 256) ? lds_sentinel<C>() : r2;
@@ -231,18 +307,36 @@ __device__ __forceinline__ void cohesion_sums_lds(PsiPair<C> (*ring)[BLOCK], int
     }
 }
 
+// Lane of stencil position n, or of its ghost when the position lies
+// beyond an open x edge (left of the inlet, right of the outflow): the node
+// of the same row clamped into the domain.  `open` says which.
+template <bool BND>
+__device__ __forceinline__ int stencil_lane(int n, int tid, int col, int nx, unsigned flags, bool &open)
+{
+    open = false;
+    if constexpr (!BND) return tid + sx(n);
+    const int pc = col + sx(n);
+    open = ((flags & FL_INLET) && pc < 0) || ((flags & FL_OUTFLOW) && pc >= nx);
+    return tid + sx(n) + (!open ? 0 : pc < 0 ? -pc : nx - 1 - pc);
+}
+
 // Stencil value at position n after the wall rules of Sec. 2.4 / Table 1,
 // resolved on the fly from the ring (at most two LDS reads): an unavailable
 // first-layer position reads zero (or psi(x) under WALLPSI_SELF); an
 // unavailable second-layer position reads what its Table 1 partner
-// resolves to (zero under E8_COPY_OFF).  Same rules as apply_wall_rules.
-template <class C, int BLOCK, int RS = 8>
+// resolves to (zero under E8_COPY_OFF).  Beyond an open edge a first-layer
+// position reads its ghost (when fluid) and a second-layer one takes the
+// Table 1 copy.  `solid` is the switch s of Eq. 9 at the position (beyond
+// an open edge: at its ghost).  Same rules as apply_wall_rules.
+template <class C, int BLOCK, int RS, bool BND>
 __device__ __forceinline__ PsiPair<C> resolve_position(PsiPair<C> (*vr)[BLOCK], int n, int y, int tid,
-                                                       C r1, C r2, unsigned flags, bool &unavailable)
+                                                       int col, int nx, C r1, C r2, unsigned flags, bool &solid)
 {
-    const PsiPair<C> v = vr[ring_slot<RS>(y + sy(n))][tid + sx(n)];
-    unavailable = lds_sent(v.a);
-    if (!unavailable) return v;
+    bool open;
+    const int lane = stencil_lane<BND>(n, tid, col, nx, flags, open);
+    const PsiPair<C> v = vr[ring_slot<RS>(y + sy(n))][lane];
+    solid = lds_sent(v.a);
+    if (!solid && (!open || n < 8)) return v;
     PsiPair<C> self, zero;
     self.a = r1;
     self.b = r2;
@@ -252,32 +346,32 @@ __device__ __forceinline__ PsiPair<C> resolve_position(PsiPair<C> (*vr)[BLOCK], 
     if (n < 8) return first_rule;
     if (flags & FL_COPY_OFF) return zero;
     const int m = table1(n);
-    const PsiPair<C> w = vr[ring_slot<RS>(y + sy(m))][tid + sx(m)];
+    bool open_m;
+    const int lane_m = stencil_lane<BND>(m, tid, col, nx, flags, open_m);
+    const PsiPair<C> w = vr[ring_slot<RS>(y + sy(m))][lane_m];
     return lds_sent(w.a) ? first_rule : w;
 }
 
 // Cohesion and adhesion sums at a node with unavailable stencil positions:
 // the same pair order as cohesion_sums / adhesion_vector, positions
-// resolved by the wall rules, S(x) from the unavailable positions.
-template <class C, int BLOCK, int RS = 8>
-__device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int tid, C r1, C r2, unsigned flags,
-                                          C &s1x, C &s1y, C &s2x, C &s2y, C &Sx, C &Sy, uint32_t &unav)
+// resolved by the wall rules, S(x) from the solid switches.
+template <class C, int BLOCK, int RS, bool BND>
+__device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int tid, int col, int nx, C r1, C r2,
+                                          unsigned flags, C &s1x, C &s1y, C &s2x, C &s2y, C &Sx, C &Sy)
 {
     // read the stencil afresh rather than keeping the bulk path's values
     // alive across the branch (a compiler-only memory clobber, no code)
     asm volatile("" ::: "memory");
     s1x = 0; s1y = 0; s2x = 0; s2y = 0;
     Sx = 0; Sy = 0;
-    unav = 0;
 #pragma unroll
     for (int g = 0; g < 6; ++g) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int n = 4 * g + h, o = n + 2;
             bool un, uo;
-            const PsiPair<C> a = resolve_position<C, BLOCK, RS>(vr, n, y, tid, r1, r2, flags, un);
-            const PsiPair<C> b = resolve_position<C, BLOCK, RS>(vr, o, y, tid, r1, r2, flags, uo);
-            unav |= ((uint32_t)un << n) | ((uint32_t)uo << o);
+            const PsiPair<C> a = resolve_position<C, BLOCK, RS, BND>(vr, n, y, tid, col, nx, r1, r2, flags, un);
+            const PsiPair<C> b = resolve_position<C, BLOCK, RS, BND>(vr, o, y, tid, col, nx, r1, r2, flags, uo);
             const C cx = (C)(e8wn(n) * sx(n));
             const C cy = (C)(e8wn(n) * sy(n));
             const C d1 = a.a - b.a;
@@ -360,28 +454,36 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
     // them into NaN and selects the wall path
     C s1x, s1y, s2x, s2y;
     cohesion_sums_lds<C, BLOCK, RS>(ring, y, tid, s1x, s1y, s2x, s2y);
-    uint32_t unav = 0;
     C Sx = 0, Sy = 0;
     const bool near = __builtin_isnan(s1x + s1y + s2x + s2y);
     if (near) {
-        wall_sums<C, BLOCK, RS>(ring, y, tid, r1, r2, p.flags, s1x, s1y, s2x, s2y, Sx, Sy, unav);
+        wall_sums<C, BLOCK, RS, (MODE & M_BND) != 0>(ring, y, tid, cx.c, p.nx, r1, r2, p.flags, s1x, s1y, s2x, s2y,
+                                                    Sx, Sy);
     }
 
     if (MODE & M_TABLES) {
-        unav = 0;
+        uint32_t unav = 0;
 #pragma unroll
         for (int n = 0; n < 24; ++n) unav |= (uint32_t)lds_sent(ring[ring_slot<RS>(y + sy(n))][tid + sx(n)].a) << n;
         p.tab_link[node] = (uint8_t)(st.info & 255);
         p.tab_nw[node] = unav ? 1 : 0;
         if (unav) {
             int idx[24];
+            uint32_t rule = unav;  // positions the wall rules resolve
 #pragma unroll
             for (int n = 0; n < 24; ++n) {
                 const Axis ax = make_axis(cx.c + sx(n), p.nx, p.flags & FL_PERIODIC_X);
                 const Axis ay = make_axis(y + sy(n), p.ny, p.flags & FL_PERIODIC_Y);
                 idx[n] = (ax.ok && ay.ok) ? ay.c * p.nx + ax.c : -1;
+                bool open;
+                const int gl = stencil_lane<(MODE & M_BND) != 0>(n, tid, cx.c, p.nx, p.flags, open);
+                if (open && n < 8 && ay.ok && !lds_sent(ring[ring_slot<RS>(y + sy(n))][gl].a)) {
+                    // first layer beyond an open edge: the fluid ghost
+                    idx[n] = ay.c * p.nx + (cx.c + sx(n) < 0 ? 0 : p.nx - 1);
+                    rule &= ~(1u << n);
+                }
             }
-            apply_wall_rules<int>(idx, unav, node, -1, p.flags);
+            apply_wall_rules<int>(idx, rule, node, -1, p.flags);
 #pragma unroll
             for (int n = 0; n < 24; ++n) p.tab_src[(long long)node * 24 + n] = idx[n];
         }
@@ -609,37 +711,39 @@ __device__ __forceinline__ void process_segment(const KParams<typename Traits<S>
     const int w = x1 - x0;
     const bool active = tid < w + 4;
     const bool interior = tid >= 2 && tid < w + 2;
-    const Axis cx = make_axis(x0 - 2 + tid, p.nx, p.flags & FL_PERIODIC_X);
+    constexpr bool BND = (MODE & M_BND) != 0;
+    const Axis cx0 = make_axis(x0 - 2 + tid, p.nx, p.flags & FL_PERIODIC_X);
+    const Axis cx = BND ? open_axis(cx0, p) : cx0;
     const bool col_ok = active && cx.ok;
     const int last = y1 + 1;  // last row whose psi is needed
 
     RowState<C> ra, rb, rc;
     RawRow<S> q;
     issue_row<S>(p, mr, cx, col_ok, y0 - 2, q);
-    process_row<S, BLOCK>(p, mr, cx, col_ok, y0 - 2, q, ring, ra);
+    process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y0 - 2, q, ring, ra);
     issue_row<S>(p, mr, cx, col_ok, y0 - 1, q);
-    process_row<S, BLOCK>(p, mr, cx, col_ok, y0 - 1, q, ring, ra);
+    process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y0 - 1, q, ring, ra);
     issue_row<S>(p, mr, cx, col_ok, y0, q);
-    process_row<S, BLOCK>(p, mr, cx, col_ok, y0, q, ring, ra);
+    process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y0, q, ring, ra);
     issue_row<S>(p, mr, cx, col_ok, y0 + 1, q);
-    process_row<S, BLOCK>(p, mr, cx, col_ok, y0 + 1, q, ring, rb);
+    process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y0 + 1, q, ring, rb);
     issue_row<S>(p, mr, cx, col_ok, y0 + 2, q);
     int y = y0;
     for (;;) {
         if (y >= y1) break;
-        process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rc);
+        process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y + 2, q, ring, rc);
         if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
         if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, y, ra, ring, acc);
         ++y;
         if (y >= y1) break;
-        process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, ra);
+        process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y + 2, q, ring, ra);
         if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
         if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, y, rb, ring, acc);
         ++y;
         if (y >= y1) break;
-        process_row<S, BLOCK>(p, mr, cx, col_ok, y + 2, q, ring, rb);
+        process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y + 2, q, ring, rb);
         if (y + 3 <= last) issue_row<S>(p, mr, cx, col_ok, y + 3, q);
         __syncthreads();
         if (interior) finish_node<S, BLOCK, MODE>(p, mw, cx, y, y, rc, ring, acc);
@@ -713,14 +817,16 @@ __device__ __forceinline__ void process_unit(const KParams<typename Traits<S>::C
 // ---------------------------------------------------------------------------
 constexpr int TWO_PR = 5;  // rows in each psi ring
 
-// Pull f(x, t+1) = f*(x - e_i, t) of row r from the LDS (lane = column).
+// Pull f(x, t+1) = f*(x - e_i, t) of row r from the LDS (lane = column);
+// the outflow column pulls the directions entering from outside from its
+// own lane (zero normal gradient, as open_axis does for HBM pulls).
 template <int S, int BLOCK>
-__device__ __forceinline__ void issue_row_lds(FRingMem<S, BLOCK> *fring, int r, RawRow<S> &q)
+__device__ __forceinline__ void issue_row_lds(FRingMem<S, BLOCK> *fring, int r, RawRow<S> &q, bool outflow_col)
 {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const int src = tid - qx(i);
+        const int src = (qx(i) == -1 && outflow_col) ? tid : tid - qx(i);
         const bool in = src >= 0 && src < BLOCK;
         const int lane = in ? src : tid;
         q.v[0][i] = in ? fr_at<S, BLOCK>(fring, 0, i, r - qy(i), lane) : Traits<S>::sentinel();
@@ -737,7 +843,7 @@ template <int S, int BLOCK> struct LdsReload {
     }
 };
 
-template <int S, int BLOCK>
+template <int S, int BLOCK, bool BND>
 __device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>::C> &p, FRingMem<S, BLOCK> *fring,
                                                 const Axis &cx, bool col_ok, int r,
                                                 PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
@@ -746,10 +852,10 @@ __device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>
     using C = typename Traits<S>::C;
     const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
     RawRow<S> q;
-    issue_row_lds<S, BLOCK>(fring, r, q);
+    issue_row_lds<S, BLOCK>(fring, r, q, BND && cx.okp && cx.p == cx.c);
     const LdsReload<S, BLOCK> reload{fring, r, (int)threadIdx.x};
     C r1 = 0, r2 = 0;
-    process_node_src<S>(p, reload, cx, ry, col_ok && ry.ok, q, st, r1, r2);
+    process_node_src<S, BND>(p, reload, cx, ry, col_ok && ry.ok, q, st, r1, r2);
     PsiPair<C> ps;
     ps.a = (st.info & 256) ? lds_sentinel<C>() : r1;
     ps.b = (st.info & 256) ? lds_sentinel<C>() : r2;
@@ -779,8 +885,8 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     // halo is computed twice), those of step t+1 from the second
     constexpr bool red1 = (MODE & M_REDUCE) && (MODE & M_DIAG_FIRST);
     constexpr bool red2 = (MODE & M_REDUCE) && !(MODE & M_DIAG_FIRST);
-    constexpr int M1 = (MODE & M_SR) | M_STORE | M_LDS | (red1 ? M_REDUCE : 0);
-    constexpr int M2 = (MODE & M_SR) | M_STORE | (red2 ? M_REDUCE : 0);
+    constexpr int M1 = (MODE & (M_SR | M_BND)) | M_STORE | M_LDS | (red1 ? M_REDUCE : 0);
+    constexpr int M2 = (MODE & (M_SR | M_BND)) | M_STORE | (red2 ? M_REDUCE : 0);
     const int tid = threadIdx.x;
     int x0, x1;
     if (p.strip_w > 0) {
@@ -791,7 +897,9 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
         x1 = (int)(((long long)(strip + 1) * p.nx) / p.n_strips);
     }
     const int w = x1 - x0;
-    const Axis cx = make_axis(x0 - 5 + tid, p.nx, p.flags & FL_PERIODIC_X);
+    constexpr bool BND = (MODE & M_BND) != 0;
+    const Axis cx0 = make_axis(x0 - 5 + tid, p.nx, p.flags & FL_PERIODIC_X);
+    const Axis cx = BND ? open_axis(cx0, p) : cx0;
     const bool act1 = tid < w + 10 && cx.ok;
     const bool in1 = tid >= 2 && tid < w + 8;
     const bool act2 = tid >= 3 && tid < w + 7 && cx.ok;
@@ -804,7 +912,7 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     RawRow<S> q;
     issue_row<S>(p, mr, cx, act1, p_first, q);
     auto iter = [&](int pp, RowState<C> &s1w, RowState<C> &s1f, RowState<C> &s2w, RowState<C> &s2f) {
-        if (pp <= p_pull_last) process_row<S, BLOCK, TWO_PR>(p, mr, cx, act1, pp, q, ring1, s1w);
+        if (pp <= p_pull_last) process_row<S, BLOCK, TWO_PR, BND>(p, mr, cx, act1, pp, q, ring1, s1w);
         if (pp + 1 <= p_pull_last) issue_row<S>(p, mr, cx, act1, pp + 1, q);
         __syncthreads();
         const bool fin1 = in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2;
@@ -815,7 +923,7 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
             finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, s1f, ring1, acc, fring, 0u, &pend, core);
         }
         __syncthreads();
-        if (pp - 3 >= y0 - 2 && pp - 3 <= y1 + 1) process_row_lds<S, BLOCK>(p, fring, cx, act2, pp - 3, ring2, s2w);
+        if (pp - 3 >= y0 - 2 && pp - 3 <= y1 + 1) process_row_lds<S, BLOCK, BND>(p, fring, cx, act2, pp - 3, ring2, s2w);
         __syncthreads();
         if (fin1) {
 #pragma unroll
@@ -1053,14 +1161,14 @@ k_pull_window(const KParams<typename Traits<S>::C> p, int x0, int y0, int w, int
     const long long M = (long long)w * h;
     if (q >= M) return;
     const int wx = (int)(q % w), wy = (int)(q / w);
-    const Axis cx = make_axis(x0 + wx, p.nx, p.flags & FL_PERIODIC_X);
+    const Axis cx = open_axis(make_axis(x0 + wx, p.nx, p.flags & FL_PERIODIC_X), p);
     const Axis ry = make_axis(y0 + wy, p.ny, p.flags & FL_PERIODIC_Y);
     const PopMem<S> m = make_mem<S>(p.A, p.N);
     RawRow<S> raw;
     issue_node<S>(m, p.nx, cx, ry, true, raw);
     RowState<C> st;
     C r1, r2;
-    process_node<S>(p, m, cx, ry, true, raw, st, r1, r2);
+    process_node<S, true>(p, m, cx, ry, true, raw, st, r1, r2);
     const bool solid = st.info & 256;
 #pragma unroll
     for (int k = 0; k < 2; ++k)

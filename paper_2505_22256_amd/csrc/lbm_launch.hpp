@@ -12,20 +12,25 @@ namespace lbm_host {
 // record the diagnostics of the first / second of them.
 enum Pass { P_STEP, P_STEP_REDUCE, P_FIELDS_REDUCE, P_TABLES, P_STEP2, P_STEP2_RED1, P_STEP2_RED2 };
 
-// Launch one pass on `st` with the kernel instance that `pass`, `block`
-// and the rounding mode select; returns the launch status.
+// Launch one pass on `st` with the kernel instance that `pass`, `block`,
+// the rounding mode and `bnd` (open or moving boundaries on: the instance
+// that has them compiled in) select; returns the launch status.
 template <int S>
-hipError_t launch_pass(const lbm::KParams<typename lbm::Traits<S>::C> &p, Pass pass, int block, bool sr,
+hipError_t launch_pass(const lbm::KParams<typename lbm::Traits<S>::C> &p, Pass pass, int block, bool sr, bool bnd,
                        hipStream_t st);
 
 // Resident workgroups per CU of the one-step kernel at this block size.
 template <int S>
 int step_occupancy(int block);
 
-extern template hipError_t launch_pass<lbm::ST_F64>(const lbm::KParams<double> &, Pass, int, bool, hipStream_t);
-extern template hipError_t launch_pass<lbm::ST_F32>(const lbm::KParams<float> &, Pass, int, bool, hipStream_t);
-extern template hipError_t launch_pass<lbm::ST_F16>(const lbm::KParams<float> &, Pass, int, bool, hipStream_t);
-extern template hipError_t launch_pass<lbm::ST_BF16>(const lbm::KParams<float> &, Pass, int, bool, hipStream_t);
+extern template hipError_t launch_pass<lbm::ST_F64>(const lbm::KParams<double> &, Pass, int, bool, bool,
+                                                     hipStream_t);
+extern template hipError_t launch_pass<lbm::ST_F32>(const lbm::KParams<float> &, Pass, int, bool, bool,
+                                                     hipStream_t);
+extern template hipError_t launch_pass<lbm::ST_F16>(const lbm::KParams<float> &, Pass, int, bool, bool,
+                                                     hipStream_t);
+extern template hipError_t launch_pass<lbm::ST_BF16>(const lbm::KParams<float> &, Pass, int, bool, bool,
+                                                     hipStream_t);
 extern template int step_occupancy<lbm::ST_F64>(int);
 extern template int step_occupancy<lbm::ST_F32>(int);
 extern template int step_occupancy<lbm::ST_F16>(int);

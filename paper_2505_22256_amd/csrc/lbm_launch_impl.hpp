@@ -46,40 +46,50 @@ hipError_t launch_step2_b(const KParams<typename Traits<S>::C> &p, int block, hi
     }
 }
 
-template <int S>
-hipError_t launch_pass(const KParams<typename Traits<S>::C> &p, Pass pass, int block, bool sr, hipStream_t st)
+template <int S, int B>
+hipError_t launch_pass_b(const KParams<typename Traits<S>::C> &p, Pass pass, int block, bool sr, hipStream_t st)
 {
     constexpr bool narrow = S == ST_F16 || S == ST_BF16;
     constexpr int R1 = M_REDUCE | M_DIAG_FIRST, R2 = M_REDUCE;
     if constexpr (narrow) {
         if (sr) {
             switch (pass) {
-            case P_STEP: return launch_step_b<S, M_STORE | M_SR>(p, block, st);
-            case P_STEP_REDUCE: return launch_step_b<S, M_STORE | M_REDUCE | M_SR>(p, block, st);
-            case P_STEP2: return launch_step2_b<S, M_STORE | M_SR>(p, block, st);
-            case P_STEP2_RED1: return launch_step2_b<S, M_STORE | M_SR | R1>(p, block, st);
-            case P_STEP2_RED2: return launch_step2_b<S, M_STORE | M_SR | R2>(p, block, st);
+            case P_STEP: return launch_step_b<S, B | M_STORE | M_SR>(p, block, st);
+            case P_STEP_REDUCE: return launch_step_b<S, B | M_STORE | M_REDUCE | M_SR>(p, block, st);
+            case P_STEP2: return launch_step2_b<S, B | M_STORE | M_SR>(p, block, st);
+            case P_STEP2_RED1: return launch_step2_b<S, B | M_STORE | M_SR | R1>(p, block, st);
+            case P_STEP2_RED2: return launch_step2_b<S, B | M_STORE | M_SR | R2>(p, block, st);
             default: break;  // field and table passes do not store
             }
         }
     }
     switch (pass) {
-    case P_STEP: return launch_step_b<S, M_STORE>(p, block, st);
-    case P_STEP_REDUCE: return launch_step_b<S, M_STORE | M_REDUCE>(p, block, st);
-    case P_FIELDS_REDUCE: return launch_step_t<S, 256, M_FIELDS | M_REDUCE>(p, st);
-    case P_TABLES: return launch_step_t<S, 256, M_TABLES>(p, st);
+    case P_STEP: return launch_step_b<S, B | M_STORE>(p, block, st);
+    case P_STEP_REDUCE: return launch_step_b<S, B | M_STORE | M_REDUCE>(p, block, st);
+    case P_FIELDS_REDUCE:
+    case P_TABLES: return hipErrorInvalidValue;  // launched by launch_pass
     case P_STEP2:
     case P_STEP2_RED1:
     case P_STEP2_RED2:
         if constexpr (S == ST_F64) {
             return hipErrorInvalidValue;  // refused by lbm_set_tile
         } else {
-            return pass == P_STEP2 ? launch_step2_b<S, M_STORE>(p, block, st)
-                 : pass == P_STEP2_RED1 ? launch_step2_b<S, M_STORE | R1>(p, block, st)
-                                        : launch_step2_b<S, M_STORE | R2>(p, block, st);
+            return pass == P_STEP2 ? launch_step2_b<S, B | M_STORE>(p, block, st)
+                 : pass == P_STEP2_RED1 ? launch_step2_b<S, B | M_STORE | R1>(p, block, st)
+                                        : launch_step2_b<S, B | M_STORE | R2>(p, block, st);
         }
     }
     return hipErrorInvalidValue;
+}
+
+// Stepping passes take the instance without boundary code unless open or
+// moving boundaries are on; the (rare) field and table passes always have it.
+template <int S>
+hipError_t launch_pass(const KParams<typename Traits<S>::C> &p, Pass pass, int block, bool sr, bool bnd, hipStream_t st)
+{
+    if (pass == P_FIELDS_REDUCE) return launch_step_t<S, 256, M_BND | M_FIELDS | M_REDUCE>(p, st);
+    if (pass == P_TABLES) return launch_step_t<S, 256, M_BND | M_TABLES>(p, st);
+    return bnd ? launch_pass_b<S, M_BND>(p, pass, block, sr, st) : launch_pass_b<S, 0>(p, pass, block, sr, st);
 }
 
 template <int S, int BLOCK>

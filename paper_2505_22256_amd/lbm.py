@@ -23,6 +23,7 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 PERIODIC_X, PERIODIC_Y = 1, 2
 SCHEME_ORIGINAL, E8_COPY_OFF, WALLPSI_SELF, VEL_LITERAL, FORCE_DENSITY = 4, 8, 16, 32, 64
 ROUND_STOCHASTIC = 128
+INLET, OUTFLOW = 256, 512
 WALL_FLAT, WALL_CYLINDER = 0, 1
 SCHED_ALIGN, SCHED_BANDS, SCHED_XCD_SLABS, SCHED_TWO_STEP = 1, 2, 4, 8
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
@@ -47,6 +48,8 @@ SIGNATURES = {
     "lbm_set_params": (_I, [_P, _D, _D, _D]),
     "lbm_set_adhesion": (_I, [_P, _D, _D, _D]),
     "lbm_set_body_accel": (_I, [_P, _D, _D, _D, _D]),
+    "lbm_set_wall_velocity": (_I, [_P, _D, _D, _D, _D]),
+    "lbm_set_inlet_velocity": (_I, [_P, _P, _P]),
     "lbm_init_fields": (_I, [_P, _P, _P]),
     "lbm_set_populations": (_I, [_P, _P]),
     "lbm_get_populations": (_I, [_P, _P]),
@@ -175,6 +178,14 @@ class Lattice:
     def set_body_accel(self, g1x, g1y, g2x, g2y):
         self._c(self._L.lbm_set_body_accel(self.h, g1x, g1y, g2x, g2y))
 
+    def set_wall_velocity(self, ubx, uby, utx, uty):
+        self._c(self._L.lbm_set_wall_velocity(self.h, ubx, uby, utx, uty))
+
+    def set_inlet_velocity(self, ux, uy):
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(ux, dtype=np.float64), (self.ny,)))
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(uy, dtype=np.float64), (self.ny,)))
+        self._c(self._L.lbm_set_inlet_velocity(self.h, _ptr(a), _ptr(b)))
+
     def init_fields(self, rho1, rho2):
         r1 = np.ascontiguousarray(rho1, dtype=np.float64).reshape(self.shape)
         r2 = np.ascontiguousarray(rho2, dtype=np.float64).reshape(self.shape)
@@ -274,6 +285,10 @@ def lattice_from_workload(wl, storage: int = F32, flags_extra: int = 0) -> Latti
     lat.set_geometry(wl.solid)
     lat.set_params(wl.G_c, wl.G_ads, wl.tau)
     lat.set_body_accel(*wl.accel)
+    if any(v != 0.0 for v in wl.wall_velocity):
+        lat.set_wall_velocity(*wl.wall_velocity)
+    if wl.inlet_u is not None:
+        lat.set_inlet_velocity(wl.inlet_u[0], wl.inlet_u[1])
     lat.init_fields(wl.rho1, wl.rho2)
     return lat
 

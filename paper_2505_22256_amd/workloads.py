@@ -15,6 +15,8 @@ Workloads (sizes from the run configurations):
   porous          2048x1024 channel of random disks, displacement      (precision study)
   calibration     512 square runs, flat or cylinder walls              (batching)
   constrictions   16384x2048 channel with 64 square constrictions     (throughput)
+  cocurrent       50x100 channel, two layers, Couette or Poiseuille    (Sec. 3.1)
+  obstacle_drop   350x150 channel, droplet past a square obstacle      (Sec. 3.3)
 """
 from __future__ import annotations
 
@@ -26,6 +28,10 @@ import numpy as np
 
 PERIODIC_X = 1
 PERIODIC_Y = 2
+SCHEME_ORIGINAL = 4
+FORCE_DENSITY = 64
+INLET = 256
+OUTFLOW = 512
 
 RHO_MAJOR = 1.0
 RHO_MINOR = 0.03
@@ -57,6 +63,10 @@ class Workload:
     steps: int = 1000
     wall_kind: Optional[int] = None
     wall: Optional[Tuple[float, float, float]] = None
+    # sliding walls: (ubx, uby, utx, uty) of the solid rows below / above ny/2
+    wall_velocity: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
+    # inlet velocity per row, float64 [2, ny] (with the INLET flag)
+    inlet_u: Optional[np.ndarray] = None
 
     @property
     def n_nodes(self) -> int:
@@ -199,13 +209,16 @@ def calibration_runs(seed: int = 22256, nruns: int = 512, steps: int = 10000) ->
 
 
 def constrictions(nx: int = 16384, ny: int = 2048, seed: int = 355, n_squares: int = 64,
-                  side: int = 128, steps: int = 100000) -> Workload:
+                  side: int = 128, steps: int = 100000, open_ends: bool = False,
+                  u_inlet: float = 0.01) -> Workload:
     """Long walled microchannel with a seeded row of square constrictions.
 
     Square j starts at x0 = (nx / n_squares) j + U_int[32, 96] and is attached
     to the bottom wall (rows [1, 1+side)) or the top wall (rows
     [ny-1-side, ny-1)) by a fair coin, drawn in that order.  Component 1
-    fills y < ny/2, component 2 the rest; both are driven along x."""
+    fills y < ny/2, component 2 the rest; both are driven along x.  Periodic
+    in x, or with `open_ends` a Zou-He inlet (Poiseuille profile of peak
+    `u_inlet`) at x = 0 and an outflow at x = nx-1."""
     rng = np.random.default_rng(seed)
     solid = np.zeros((ny, nx), dtype=np.uint8)
     solid[0, :] = 1
@@ -218,8 +231,74 @@ def constrictions(nx: int = 16384, ny: int = 2048, seed: int = 355, n_squares: i
         solid[y0:y0 + side, x0:x0 + side] = 1
     _, y = _grid(nx, ny)
     rho1, rho2 = _two_phase(y < ny / 2.0, solid)
+    if open_ends:
+        return Workload("constrictions_open", nx, ny, INLET | OUTFLOW, solid, rho1, rho2, G_c=0.9, G_ads=0.15,
+                        tau=1.0, accel=(2e-6, 0.0, 2e-6, 0.0), steps=steps,
+                        inlet_u=poiseuille_profile(ny, u_inlet))
     return Workload("constrictions", nx, ny, PERIODIC_X, solid, rho1, rho2, G_c=0.9, G_ads=0.15,
                     tau=1.0, accel=(2e-6, 0.0, 2e-6, 0.0), steps=steps)
+
+
+def poiseuille_profile(ny: int, u_max: float) -> np.ndarray:
+    """Inlet rows of a channel walled at rows 0 and ny-1: the parabola
+    u_x = 4 u_max eta (1 - eta), eta = (y - 1/2) / (ny - 2), through the
+    halfway wall planes (the profile -4 U_m y (y - H) / H^2 of Sec. 3.3);
+    u_y = 0.  Returns [2, ny] (wall rows 0)."""
+    y = np.arange(ny, dtype=np.float64)
+    eta = (y - 0.5) / (ny - 2)
+    u = np.zeros((2, ny))
+    u[0] = 4.0 * u_max * eta * (1.0 - eta)
+    u[0, 0] = 0.0
+    u[0, ny - 1] = 0.0
+    return u
+
+
+def cocurrent(flow: str = "couette", nx: int = 50, ny: int = 102, a: float = 25.0, G_ads: float = 0.0,
+              u_wall: float = 0.005, force: float = 1e-6, tau: float = 1.01, major: float = 1.02,
+              minor: float = 0.05, steps: int = 10000) -> Workload:
+    """Co-current flow of two layers between walls (Sec. 3.1): 100 fluid
+    rows between solid rows 0 and ny-1, periodic in x; component 1 in the
+    central layer |y - yc| <= a, component 2 outside (main 1.02, dissolved
+    0.05, nu = 0.17 so tau = 1.01).  Couette: the walls slide at -u_wall
+    (bottom) and +u_wall (top); Poiseuille: a body force density `force`
+    on both components along x."""
+    x, y = _grid(nx, ny)
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[ny - 1, :] = 1
+    yc = (ny - 1) / 2.0
+    rho1, rho2 = _two_phase(np.abs(y - yc) <= a, solid, major, minor)
+    if flow == "couette":
+        return Workload("couette", nx, ny, PERIODIC_X, solid, rho1, rho2, G_c=0.9, G_ads=G_ads, tau=tau,
+                        steps=steps, wall_velocity=(-u_wall, 0.0, u_wall, 0.0))
+    if flow == "poiseuille":
+        return Workload("poiseuille", nx, ny, PERIODIC_X | FORCE_DENSITY, solid, rho1, rho2, G_c=0.9,
+                        G_ads=G_ads, tau=tau, steps=steps, accel=(force, 0.0, force, 0.0))
+    raise ValueError(flow)
+
+
+def obstacle_drop(nx: int = 350, ny: int = 150, side: int = 25, centre=(122.0, 75.0), r_drop: float = 25.0,
+                  drop_centre=(55.0, 75.0), G_ads: float = -0.2, tau: float = 1.01, reynolds: float = 7.5,
+                  steps: int = 10000) -> Workload:
+    """Droplet carried past a square obstacle in a microchannel (Sec. 3.3):
+    walls at rows 0 and ny-1, a square of side `side` centred at `centre`,
+    droplet (component 1) of radius r at `drop_centre`, component 2
+    elsewhere.  Zou-He inlet at x = 0 with the Poiseuille profile, outflow
+    at x = nx-1.  u_max from Re = u_max (2 r) / nu with nu = (tau - 1/2)/3;
+    G_ads = -0.2 puts the static angle near the configured 30 degrees."""
+    x, y = _grid(nx, ny)
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[ny - 1, :] = 1
+    h = side / 2.0
+    sq = (np.abs(x - centre[0]) < h) & (np.abs(y - centre[1]) < h)
+    solid[sq] = 1
+    inside = (x - drop_centre[0]) ** 2 + (y - drop_centre[1]) ** 2 < r_drop * r_drop
+    rho1, rho2 = _two_phase(inside, solid)
+    nu = (tau - 0.5) / 3.0
+    u_max = reynolds * nu / (2.0 * r_drop)
+    return Workload("obstacle_drop", nx, ny, INLET | OUTFLOW, solid, rho1, rho2, G_c=0.9, G_ads=G_ads,
+                    tau=tau, steps=steps, inlet_u=poiseuille_profile(ny, u_max))
 
 
 def random_small(seed: int, nx: int = 24, ny: int = 18, flags: int = PERIODIC_X | PERIODIC_Y,

@@ -55,7 +55,7 @@ def test_flag_and_code_values_match_the_header():
     from paper_2505_22256_amd import lbm
     text = open(os.path.join(ROOT, "include", "lbm.h")).read()
     for name in ("PERIODIC_X", "PERIODIC_Y", "SCHEME_ORIGINAL", "E8_COPY_OFF", "WALLPSI_SELF",
-                 "VEL_LITERAL", "FORCE_DENSITY", "ROUND_STOCHASTIC", "SCHED_ALIGN", "SCHED_BANDS", "SCHED_XCD_SLABS", "SCHED_TWO_STEP", "F64", "F32", "F16", "BF16", "EINVAL", "ESTATE",
+                 "VEL_LITERAL", "FORCE_DENSITY", "ROUND_STOCHASTIC", "INLET", "OUTFLOW", "SCHED_ALIGN", "SCHED_BANDS", "SCHED_XCD_SLABS", "SCHED_TWO_STEP", "F64", "F32", "F16", "BF16", "EINVAL", "ESTATE",
                  "EDEVICE", "EUNSTABLE", "WALL_FLAT", "WALL_CYLINDER"):
         m = re.search(r"LBM_%s\s*=\s*(-?\d+)" % name, text)
         assert m, name
