@@ -117,3 +117,52 @@ def test_full_lattice_mass_and_finiteness(lbm_mod, channel):
         assert abs(m1[k] - m0[k]) / m0[k] < 1e-5
     # the body force drives both components along +x
     assert m1[2] > 0
+
+
+def _open_samples(wl, seed=5):
+    """Random fluid and near-wall nodes, plus nodes of the four columns at
+    each open edge (the Zou-He unknowns, the outflow copy, the E8 ghosts
+    and Table 1 copies beyond the edge)."""
+    rng = np.random.default_rng(seed)
+    base = _samples(wl, n_each=12, seed=seed)[:24]
+    edge_cols = [0, 1, 2, 3, wl.nx - 4, wl.nx - 3, wl.nx - 2, wl.nx - 1]
+    ys = rng.integers(1, wl.ny - 1, size=len(edge_cols))
+    ys[:2] = 1           # the inlet corner on the bottom wall
+    ys[-2:] = wl.ny - 2  # the outflow corner on the top wall
+    edge = np.array([(y, x) for y, x in zip(ys, edge_cols) if wl.solid[y, x] == 0])
+    return np.concatenate([base, edge])
+
+
+@pytest.mark.parametrize("storage,tol", [(1, 2e-6)])
+def test_open_channel_sampled_nodes_against_oracle(oracle_mod, lbm_mod, storage, tol):
+    """The channel with a Zou-He inlet and an outflow instead of periodic x,
+    in the launch configuration of the open-channel benchmark (default
+    tile, boundary kernel instances): sampled nodes, open-edge columns
+    included, advance one launch as the oracle advances their windows; a
+    window that reaches an open edge carries that edge (and the inlet
+    velocities of its rows)."""
+    wl = W.constrictions(open_ends=True)
+    g = lbm_mod.lattice_from_workload(wl, storage)
+    n = 2 if g.get_tile()[2] & lbm_mod.SCHED_TWO_STEP else 1
+    rad = 3 * n
+    g.step(41)
+    samples = _open_samples(wl)
+    before = []
+    for (y, x) in samples:
+        y0, x0 = max(0, y - rad), max(0, x - rad)
+        h, w = min(wl.ny, y + rad + 1) - y0, min(wl.nx, x + rad + 1) - x0
+        before.append((y0, x0, h, w, g.get_populations_window(x0, y0, w, h)))
+    g.step(n)
+    for (y, x), (y0, x0, h, w, f_win) in zip(samples, before):
+        flags = (W.INLET if x0 == 0 else 0) | (W.OUTFLOW if x0 + w == wl.nx else 0)
+        o = oracle_mod.Oracle(w, h, flags)
+        o.set_geometry(wl.solid[y0:y0 + h, x0:x0 + w])
+        o.set_params(wl.G_c, wl.G_ads, wl.tau)
+        o.set_body_accel(*wl.accel)
+        o.set_inlet_velocity(wl.inlet_u[0, y0:y0 + h], wl.inlet_u[1, y0:y0 + h])
+        o.set_populations(f_win)
+        o.step(n)
+        ref = o.get_populations()[:, :, y - y0, x - x0]
+        after = g.get_populations_window(x, y, 1, 1)[:, :, 0, 0]
+        err = np.max(np.abs(after - ref)) / np.max(np.abs(ref))
+        assert err < tol, (int(y), int(x), err)
