@@ -1,6 +1,6 @@
 """Full-size checks on the 16384 x 2048 constriction channel, in the launch
 configuration the benchmark times (the library's default tile: two fused
-steps per launch for FP32, one for FP16), and on the 2048 x 1024 porous
+steps per launch for FP32 and FP16), and on the 2048 x 1024 porous
 channel of the precision study (FP64, anchored at t = 1000).
 
 The oracle cannot step the whole lattice in test time, so it checks sampled
