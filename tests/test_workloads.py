@@ -99,3 +99,52 @@ def test_saturation_and_front_helper():
     s1, front = bench.saturation_and_front(wl, r1, r2)
     assert front == 9
     assert abs(s1 - 11 * 18 / (40 * 18)) < 1e-15
+
+
+def test_poiseuille_inlet_profile():
+    """The inlet parabola goes through the halfway wall planes: zero on the
+    solid rows, peak u_max midway, symmetric, no transverse part."""
+    u = W.poiseuille_profile(102, 0.02)
+    assert u.shape == (2, 102)
+    assert u[0, 0] == 0.0 and u[0, -1] == 0.0 and np.all(u[1] == 0.0)
+    assert np.allclose(u[0, 1:-1], u[0, 1:-1][::-1], rtol=0, atol=1e-17)
+    eta = (np.arange(102) - 0.5) / 100
+    assert np.allclose(u[0, 1:-1], 0.08 * eta[1:-1] * (1 - eta[1:-1]), rtol=1e-15)
+    assert abs(u[0].max() - 0.02 * (1 - (0.5 / 50) ** 2)) < 1e-15
+
+
+def test_cocurrent_recipes():
+    c = W.cocurrent("couette")
+    p = W.cocurrent("poiseuille")
+    for wl in (c, p):
+        assert (wl.nx, wl.ny) == (50, 102)
+        assert wl.solid[0].all() and wl.solid[-1].all() and not wl.solid[1:-1].any()
+        assert abs(wl.tau - (3 * 0.17 + 0.5)) < 1e-12
+        y = np.arange(102)
+        core = np.abs(y - 50.5) <= 25
+        assert np.all(wl.rho1[1:-1][core[1:-1]] == 1.02) and np.all(wl.rho1[1:-1][~core[1:-1]] == 0.05)
+    assert c.wall_velocity == (-0.005, 0.0, 0.005, 0.0) and c.flags == W.PERIODIC_X
+    assert p.accel == (1e-6, 0.0, 1e-6, 0.0) and p.flags & W.FORCE_DENSITY
+    with pytest.raises(ValueError):
+        W.cocurrent("stokes")
+
+
+def test_obstacle_drop_recipe():
+    wl = W.obstacle_drop()
+    assert (wl.nx, wl.ny) == (350, 150) and wl.flags == W.INLET | W.OUTFLOW
+    inner = wl.solid[1:-1]
+    assert inner.sum() == 25 * 25  # the square, |x - 122|, |y - 75| < 12.5
+    ys, xs = np.nonzero(inner)
+    assert (xs.min(), xs.max(), ys.min() + 1, ys.max() + 1) == (110, 134, 63, 87)
+    drop = (wl.rho1 > wl.rho2) & (wl.solid == 0)
+    assert abs(drop.sum() - math.pi * 25 ** 2) < 2 * math.pi * 25
+    nu = (wl.tau - 0.5) / 3
+    assert abs(wl.inlet_u[0].max() - 7.5 * nu / 50 * (1 - (0.5 / 74) ** 2)) < 1e-12
+
+
+def test_open_constriction_channel_recipe():
+    a, b = W.constrictions(nx=512, ny=64, n_squares=2, side=8), W.constrictions(nx=512, ny=64, n_squares=2, side=8,
+                                                                               open_ends=True)
+    assert np.array_equal(a.solid, b.solid) and np.array_equal(a.rho1, b.rho1)
+    assert a.flags == W.PERIODIC_X and b.flags == W.INLET | W.OUTFLOW
+    assert b.inlet_u.shape == (2, 64) and b.inlet_u[0].max() <= 0.01
