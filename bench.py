@@ -49,6 +49,9 @@ def kernel_source_hash() -> str:
     for name in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp"):
         with open(os.path.join(ROOT, "paper_2505_22256_amd", "csrc", name), "rb") as f:
             h.update(f.read())
+    # the compiler flags shape the kernels too
+    from paper_2505_22256_amd import build as _build
+    h.update(" ".join(_build.FLAGS[:-4]).encode())
     return h.hexdigest()[:16]
 
 

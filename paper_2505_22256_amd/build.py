@@ -2,7 +2,11 @@
 
 hipcc compiles the device code for gfx950 only.  Packed FP32 instructions
 are disabled (-packed-fp32-ops); hipcc's host pass warns that it does not
-know the feature, which is harmless.
+know the feature, which is harmless.  Mixed-precision fused multiply-adds
+(-fma-mix-insts, which fold the FP32-to-FP16 store conversion into the last
+multiply-add of the collision) are disabled too: the separate multiply-add
+and conversion run 2 % faster in the FP16 step kernels, and the results
+stay bitwise independent of the tiling.
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ HEADERS = [os.path.join(CSRC, n) for n in ("lbm_device.hpp", "lbm_kernels.hpp", 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-fma-mix-insts",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
