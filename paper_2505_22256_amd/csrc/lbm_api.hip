@@ -344,7 +344,7 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
     c->solid.assign((size_t)c->N, 0);
     // measured defaults on the 16384 x 2048 channel: FP32 fuses two steps
     // per launch (128-thread strips, 24-row segments in row bands), FP16
-    // too in 64-thread strips of 32-row segments (2.6 % over one step);
+    // too in 64-thread strips of 32-row segments (4 % over one step);
     // BF16 (issue-bound, slower fused) and FP64 run one step per launch in
     // 16-row segments and row bands, FP64 with 128-byte aligned strips
     if (storage == LBM_F32) {
