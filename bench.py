@@ -69,9 +69,11 @@ def measured_traffic(storage_name: str, tile):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, seconds: float = 12.0):
+def cpu_baseline(wl, seconds: float = 12.0, single_seconds: float = 6.0):
     """FP64 oracle on a bounded sample of the same workload: the first 1024
-    columns of the channel (periodic in x), stepped until `seconds` pass."""
+    columns of the channel (periodic in x), stepped until `seconds` pass on
+    all the host threads it uses, then for `single_seconds` on one thread
+    (the per-core figure)."""
     import oracle  # the oracle: CPU baseline only
     oracle.build(force=False)
     w = 1024
@@ -82,17 +84,26 @@ def cpu_baseline(wl, seconds: float = 12.0):
     o.init_fields(wl.rho1[:, :w], wl.rho2[:, :w])
     o.step(1)
     nf = int(w * wl.ny - wl.solid[:, :w].sum())
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        o.step(2)
-        steps += 2
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": round(nf * steps / el / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+
+    def timed(limit):
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            o.step(2)
+            steps += 2
+            el = time.perf_counter() - t0
+            if el >= limit:
+                return steps, el
+
+    cores = oracle.threads()
+    steps, el = timed(seconds)
+    prev = oracle.set_threads(1)
+    steps1, el1 = timed(single_seconds)
+    oracle.set_threads(prev)
+    return {"value": round(nf * steps / el / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
+            "single_core_value": round(nf * steps1 / el1 / 1e6, 3),
             "sample": f"constriction channel columns 0..{w - 1} x {wl.ny} rows (periodic in x), "
-                      f"{steps} FP64 steps, {el:.1f} s"}
+                      f"{steps} FP64 steps in {el:.1f} s on {cores} threads, {steps1} in {el1:.1f} s on one"}
 
 
 def precision_check(steps: int = 5000):

@@ -75,6 +75,7 @@ def lib():
             "oracle_adhesion_vector": (I, [P, I, I, P]),
             "oracle_circle_fit": (I, [P, P, I, P]),
             "oracle_threads": (I, []),
+            "oracle_set_threads": (I, [I]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -256,3 +257,9 @@ def circle_fit(px, py):
 
 def threads():
     return lib().oracle_threads()
+
+
+def set_threads(n):
+    """Threads of the oracle's row loops (results are independent of it);
+    returns the previous count."""
+    return lib().oracle_set_threads(int(n))

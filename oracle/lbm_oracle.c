@@ -979,3 +979,16 @@ int oracle_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the row loops from now on (n >= 1); results do not depend
+ * on it.  Returns the previous count. */
+int oracle_set_threads(int n)
+{
+    int prev = oracle_threads();
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return prev;
+}

@@ -103,6 +103,7 @@ int oracle_get_tables(const oracle_ctx *c, uint8_t *link, int32_t *nw_list,
 
 /* OpenMP threads the row loops use (1 without OpenMP). */
 int oracle_threads(void);
+int oracle_set_threads(int n);
 
 /* ---- pieces exposed for unit pins ---- */
 void oracle_d2q9(int ex[9], int ey[9], double w[9], int opp[9]);
