@@ -111,6 +111,30 @@ enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
  * Errors: EINVAL (sizes, storage, flags), ENOMEM, EDEVICE (no gfx950 GPU). */
 int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags);
 
+/* As lbm_create, but the two population buffers are the caller's device
+ * memory (for instance two torch tensors' data_ptr on the current device),
+ * so that a caller can read or write the state in place.  Each must hold
+ * lbm_population_bytes(nx, ny, storage) bytes, be 256-byte aligned, lie on
+ * the current device and not overlap the other.  The library never frees
+ * them; they must stay valid until lbm_destroy.  Layout of each: the
+ * storage type's elements as [component 2][direction 9][y][x], directions
+ * e_0 = (0,0), e_1..e_4 = (1,0), (0,1), (-1,0), (0,-1), e_5..e_8 = (1,1),
+ * (-1,1), (-1,-1), (1,-1); solid nodes hold all-ones bit patterns.
+ * The buffer lbm_current_buffer names holds the post-collision populations
+ * of the last step, f*(x, t-1) (after lbm_init_fields or lbm_set_populations
+ * the state as set); the next step pulls f_i(x, t) = f*_i(x - e_i, t-1), or
+ * the bounce-back at a wall link, from it.  The other buffer is scratch.
+ * For F32, F16 and BF16 storage the values are the deviations of the
+ * storage-type comment above.  Errors: as lbm_create, and EINVAL for a null,
+ * misaligned, too small, overlapping or non-device buffer. */
+int lbm_create_ex(lbm_ctx **out, int nx, int ny, int storage, unsigned flags, void *buf_a, void *buf_b,
+                  size_t bytes_each);
+/* Bytes of one population buffer: 18*nx*ny elements of the storage type
+ * (0 for sizes or a storage lbm_create refuses). */
+size_t lbm_population_bytes(int nx, int ny, int storage);
+/* 0 for buf_a, 1 for buf_b: the buffer that holds the current state. */
+int lbm_current_buffer(const lbm_ctx *c);
+
 /* Solid mask, ny*nx bytes, 0 = fluid, non-zero = solid (the switch s(x) of
  * Eq. 9).  Copied.  Invalidates the populations (init again). */
 int lbm_set_geometry(lbm_ctx *c, const uint8_t *solid);

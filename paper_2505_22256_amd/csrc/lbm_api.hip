@@ -24,6 +24,7 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;
     void *buf[2] = {nullptr, nullptr};
+    bool ext_buf = false;  // buf[] belongs to the caller (lbm_create_ex)
     int cur = 0;  // buffer holding the post-collision set of the previous step
     uint8_t *d_solid = nullptr;
     double *d_tmp = nullptr;  // staging: fields (4N doubles) or populations (18N)
@@ -295,7 +296,8 @@ using namespace lbm_host;
 
 extern "C" {
 
-int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
+static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags, void *ext_a, void *ext_b,
+                      size_t ext_bytes)
 {
     if (!out) return LBM_EINVAL;
     *out = nullptr;
@@ -324,12 +326,36 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
         return LBM_EDEVICE;
     }
     const size_t bytes = (size_t)c->N * 18 * elem_size(storage);
+    if (ext_a || ext_b) {
+        // the caller's buffers: device memory of this device, distinct,
+        // not overlapping, aligned and large enough
+        bool good = ext_a && ext_b && ext_bytes >= bytes && ((uintptr_t)ext_a % 256) == 0 &&
+                    ((uintptr_t)ext_b % 256) == 0;
+        if (good) {
+            uintptr_t a = (uintptr_t)ext_a, b = (uintptr_t)ext_b;
+            good = a + bytes <= b || b + bytes <= a;
+        }
+        for (void *p : {ext_a, ext_b}) {
+            hipPointerAttribute_t at;
+            if (good && (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice ||
+                         at.device != c->device))
+                good = false;
+        }
+        (void)hipGetLastError();  // a failed attribute query leaves no error behind
+        if (!good) {
+            delete c;
+            return LBM_EINVAL;
+        }
+        c->buf[0] = ext_a;
+        c->buf[1] = ext_b;
+        c->ext_buf = true;
+    }
     if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return LBM_EDEVICE;
     }
     c->stream = c->own_stream;
-    bool ok = hipMalloc(&c->buf[0], bytes) == hipSuccess && hipMalloc(&c->buf[1], bytes) == hipSuccess &&
+    bool ok = (c->ext_buf || (hipMalloc(&c->buf[0], bytes) == hipSuccess && hipMalloc(&c->buf[1], bytes) == hipSuccess)) &&
               hipMalloc(&c->d_solid, (size_t)c->N) == hipSuccess && hipMalloc(&c->d_out, 32 * sizeof(double)) == hipSuccess &&
               hipMalloc(&c->d_inlet, (size_t)ny * 2 * sizeof(double)) == hipSuccess;
     if (!ok) {
@@ -364,12 +390,39 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
     return LBM_OK;
 }
 
+int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags)
+{
+    return create_ctx(out, nx, ny, storage, flags, nullptr, nullptr, 0);
+}
+
+int lbm_create_ex(lbm_ctx **out, int nx, int ny, int storage, unsigned flags, void *buf_a, void *buf_b,
+                  size_t bytes_each)
+{
+    if (!buf_a || !buf_b) {
+        if (out) *out = nullptr;
+        return LBM_EINVAL;
+    }
+    return create_ctx(out, nx, ny, storage, flags, buf_a, buf_b, bytes_each);
+}
+
+size_t lbm_population_bytes(int nx, int ny, int storage)
+{
+    if (nx < 5 || ny < 5 || storage < LBM_F64 || storage > LBM_BF16) return 0;
+    return (size_t)nx * (size_t)ny * 18 * elem_size(storage);
+}
+
+int lbm_current_buffer(const lbm_ctx *c)
+{
+    if (!c) return LBM_EINVAL;
+    return c->cur;
+}
+
 void lbm_destroy(lbm_ctx *c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->buf[0]) (void)hipFree(c->buf[0]);
-    if (c->buf[1]) (void)hipFree(c->buf[1]);
+    if (c->buf[0] && !c->ext_buf) (void)hipFree(c->buf[0]);
+    if (c->buf[1] && !c->ext_buf) (void)hipFree(c->buf[1]);
     if (c->d_solid) (void)hipFree(c->d_solid);
     if (c->d_tmp) (void)hipFree(c->d_tmp);
     if (c->d_partials) (void)hipFree(c->d_partials);

@@ -6,6 +6,14 @@ exceptions.  The module-level functions carry the C names; ``Lattice`` and
 ``Batch`` wrap a context for convenience.  Importing works without a GPU;
 creating a context needs an MI355X and raises ``LbmError`` otherwise.  There
 is no CPU fallback: a missing library raises at load time.
+
+Device pointers handed to the library (``Lattice(buffers=...)``, stream
+handles) must come from the HIP runtime it is bound to.  PyTorch for ROCm
+ships its own copy of that runtime under the same soname: import torch
+before the first ``load_library`` and the library binds to torch's copy,
+so torch tensors and streams are valid here; load the library first and a
+later ``import torch`` brings a second runtime whose pointers the library
+does not know (``lbm_create_ex`` then refuses them).
 """
 from __future__ import annotations
 
@@ -44,6 +52,9 @@ class LbmRunDesc(ctypes.Structure):
 # name -> (restype, argtypes); the exported symbol set of include/lbm.h
 SIGNATURES = {
     "lbm_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _U]),
+    "lbm_create_ex": (_I, [ctypes.POINTER(_P), _I, _I, _I, _U, _P, _P, ctypes.c_size_t]),
+    "lbm_population_bytes": (ctypes.c_size_t, [_I, _I, _I]),
+    "lbm_current_buffer": (_I, [_P]),
     "lbm_set_geometry": (_I, [_P, _P]),
     "lbm_set_params": (_I, [_P, _D, _D, _D]),
     "lbm_set_adhesion": (_I, [_P, _D, _D, _D]),
@@ -128,6 +139,28 @@ def lbm_create(nx: int, ny: int, storage: int = F32, flags: int = 0):
     return h
 
 
+def lbm_create_ex(nx: int, ny: int, storage: int, flags: int, buf_a: int, buf_b: int, bytes_each: int):
+    h = _P()
+    rc = load_library().lbm_create_ex(ctypes.byref(h), nx, ny, storage, flags, buf_a, buf_b, bytes_each)
+    if rc:
+        raise LbmError(rc, "lbm_create_ex failed")
+    return h
+
+
+def lbm_population_bytes(nx: int, ny: int, storage: int) -> int:
+    return load_library().lbm_population_bytes(nx, ny, storage)
+
+
+def _device_span(t):
+    """(address, bytes) of a device array given as an object with
+    data_ptr() (a torch tensor; its bytes are numel * element_size) or as an
+    (address, bytes) pair."""
+    if hasattr(t, "data_ptr"):
+        return int(t.data_ptr()), int(t.numel() * t.element_size())
+    a, n = t
+    return int(a), int(n)
+
+
 def lbm_destroy(h):
     load_library().lbm_destroy(h)
 
@@ -145,15 +178,26 @@ def _check(h, rc):
 class Lattice:
     """One context: a lattice with its geometry, parameters and state."""
 
-    def __init__(self, nx: int, ny: int, storage: int = F32, flags: int = 0):
+    def __init__(self, nx: int, ny: int, storage: int = F32, flags: int = 0, buffers=None):
+        """buffers: None (the library allocates), or two device arrays (torch
+        tensors or (address, bytes) pairs) that become the population
+        buffers (lbm_create_ex); they are kept referenced while the
+        lattice lives and never freed by the library."""
         self._L = load_library()
-        self.h = lbm_create(nx, ny, storage, flags)
+        self._ext = None
+        if buffers is None:
+            self.h = lbm_create(nx, ny, storage, flags)
+        else:
+            (pa, na), (pb, nb) = (_device_span(b) for b in buffers)
+            self.h = lbm_create_ex(nx, ny, storage, flags, pa, pb, min(na, nb))
+            self._ext = tuple(buffers)
         self.nx, self.ny, self.storage, self.flags = nx, ny, storage, flags
 
     def close(self):
         if getattr(self, "h", None):
             self._L.lbm_destroy(self.h)
             self.h = None
+        self._ext = None
 
     def __del__(self):
         self.close()
@@ -161,6 +205,13 @@ class Lattice:
     @property
     def shape(self):
         return (self.ny, self.nx)
+
+    def current_buffer(self) -> int:
+        """Index (0 or 1) of the population buffer holding the current state."""
+        rc = self._L.lbm_current_buffer(self.h)
+        if rc < 0:
+            raise LbmError(rc, "lbm_current_buffer failed")
+        return rc
 
     def _c(self, rc):
         return _check(self.h, rc)

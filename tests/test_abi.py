@@ -60,3 +60,15 @@ def test_flag_and_code_values_match_the_header():
         m = re.search(r"LBM_%s\s*=\s*(-?\d+)" % name, text)
         assert m, name
         assert int(m.group(1)) == getattr(lbm, name), name
+
+
+def test_population_bytes():
+    """Size of one caller-provided population buffer (host arithmetic only):
+    18 elements of the storage type per node, 0 for refused sizes."""
+    from paper_2505_22256_amd import lbm
+    assert lbm.lbm_population_bytes(7, 5, lbm.F64) == 7 * 5 * 18 * 8
+    assert lbm.lbm_population_bytes(16384, 2048, lbm.F32) == 16384 * 2048 * 18 * 4
+    assert lbm.lbm_population_bytes(9, 6, lbm.F16) == 9 * 6 * 18 * 2
+    assert lbm.lbm_population_bytes(9, 6, lbm.BF16) == 9 * 6 * 18 * 2
+    assert lbm.lbm_population_bytes(4, 6, lbm.F32) == 0
+    assert lbm.lbm_population_bytes(9, 6, 7) == 0
