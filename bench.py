@@ -335,8 +335,8 @@ def _timed_steps(lat, stream, steps, warmup):
 def open_channel(args):
     """The constriction channel with its x edges opened (Zou-He inlet with a
     Poiseuille profile at x = 0, outflow at x = nx-1) against the periodic
-    channel, same storage and tile: the cost of the open boundaries on the
-    hot path."""
+    channel, same storage, each at the library's default tile (or both at
+    --tile): the cost of the open boundaries on the hot path."""
     import torch
     storage = STORAGES[args.storage]
     steps = args.steps if args.steps_given else 1000
@@ -345,6 +345,9 @@ def open_channel(args):
         stream = torch.cuda.Stream()
         lat = lbm.lattice_from_workload(wl, storage)
         lat.set_stream(stream.cuda_stream)
+        if args.tile not in ("default", "auto"):
+            vals = [int(v) for v in args.tile.split(",")]
+            lat.set_tile(vals[0], vals[1], vals[2] if len(vals) > 2 else 0)
         ms = _timed_steps(lat, stream, steps, args.warmup)
         m = lat.reduce()
         out[name] = {"MLUPS": round(lat.fluid_nodes * steps / (ms * 1e-3) / 1e6, 1),

@@ -243,7 +243,8 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * width block - 4 columns) and rows per workgroup segment.  seg_rows = 0
  * is persistent scheduling: one work unit per resident workgroup, each
  * taking an equal share of the strip rows.  Default after lbm_create:
- * FP32 block 128, seg_rows 24, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; FP16
+ * FP32 block 128 (64 with LBM_INLET or LBM_OUTFLOW), seg_rows 24,
+ * LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; FP16
  * block 64, seg_rows 32, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; BF16 block
  * 256, seg_rows 16, LBM_SCHED_BANDS; FP64 block 256, seg_rows 16,
  * LBM_SCHED_ALIGN | LBM_SCHED_BANDS.  Results do not

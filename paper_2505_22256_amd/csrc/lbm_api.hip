@@ -372,9 +372,11 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     // per launch (128-thread strips, 24-row segments in row bands), FP16
     // too in 64-thread strips of 32-row segments (4 % over one step);
     // BF16 (issue-bound, slower fused) and FP64 run one step per launch in
-    // 16-row segments and row bands, FP64 with 128-byte aligned strips
+    // 16-row segments and row bands, FP64 with 128-byte aligned strips.
+    // With open x edges FP32 steps in the boundary instances (220 VGPRs
+    // against 195), which run best in 64-thread strips (2.4 % over 128)
     if (storage == LBM_F32) {
-        c->block = 128;
+        c->block = (flags & (LBM_INLET | LBM_OUTFLOW)) ? 64 : 128;
         c->seg_rows = 24;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
     } else if (storage == LBM_F16) {
