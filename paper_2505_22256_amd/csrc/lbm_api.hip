@@ -373,10 +373,12 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     // too in 64-thread strips of 32-row segments (4 % over one step);
     // BF16 (issue-bound, slower fused) and FP64 run one step per launch in
     // 16-row segments and row bands, FP64 with 128-byte aligned strips.
-    // With open x edges FP32 steps in the boundary instances (220 VGPRs
-    // against 195), which run best in 64-thread strips (2.4 % over 128)
+    // With open x edges the steps run in the boundary instances (FP32: 220
+    // VGPRs against 195), which run best in narrower strips: FP32 64 threads
+    // (2.4 % over 128), BF16 128 (1.6 % over 256)
+    const bool open_x = (flags & (LBM_INLET | LBM_OUTFLOW)) != 0;
     if (storage == LBM_F32) {
-        c->block = (flags & (LBM_INLET | LBM_OUTFLOW)) ? 64 : 128;
+        c->block = open_x ? 64 : 128;
         c->seg_rows = 24;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
     } else if (storage == LBM_F16) {
@@ -384,7 +386,7 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
         c->seg_rows = 32;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
     } else {
-        c->block = 256;
+        c->block = storage == LBM_BF16 && open_x ? 128 : 256;
         c->seg_rows = 16;
         c->sched = storage == LBM_F64 ? (SCHED_ALIGN | SCHED_BANDS) : SCHED_BANDS;
     }
