@@ -177,3 +177,21 @@ def test_open_flags_refused_where_unsupported(lbm_mod):
     wl = CASES["obstacle"]()
     with pytest.raises(lbm_mod.LbmError):
         lbm_mod.Batch([wl], lbm_mod.F32)
+
+
+def test_default_tiles_with_open_edges(lbm_mod):
+    """Measured defaults: with open x edges FP32 takes 64-thread strips and
+    BF16 128-thread ones; FP16 and FP64 keep theirs; closed lattices keep
+    the periodic channel's."""
+    want = {
+        (lbm_mod.F32, OPEN): (64, 24, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
+        (lbm_mod.F32, W.PERIODIC_X): (128, 24, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
+        (lbm_mod.BF16, OPEN): (128, 16, lbm_mod.SCHED_BANDS),
+        (lbm_mod.BF16, W.PERIODIC_X): (256, 16, lbm_mod.SCHED_BANDS),
+        (lbm_mod.F16, OPEN): (64, 32, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
+        (lbm_mod.F64, OPEN): (256, 16, lbm_mod.SCHED_ALIGN | lbm_mod.SCHED_BANDS),
+    }
+    for (storage, flags), tile in want.items():
+        g = lbm_mod.Lattice(40, 20, storage, flags)
+        assert tuple(g.get_tile()) == tile, (storage, flags)
+        g.close()
