@@ -9,11 +9,12 @@ is no CPU fallback: a missing library raises at load time.
 
 Device pointers handed to the library (``Lattice(buffers=...)``, stream
 handles) must come from the HIP runtime it is bound to.  PyTorch for ROCm
-ships its own copy of that runtime under the same soname: import torch
-before the first ``load_library`` and the library binds to torch's copy,
-so torch tensors and streams are valid here; load the library first and a
-later ``import torch`` brings a second runtime whose pointers the library
-does not know (``lbm_create_ex`` then refuses them).
+ships its own copy of that runtime under the same soname, so
+``load_library`` imports torch (when it is installed) before it loads the
+library: the library then binds to torch's copy, and torch tensors and
+streams are valid here.  A process that loaded liblbm.so by other means
+before importing torch would hold two runtimes, whose pointers the other
+does not know (``lbm_create_ex`` refuses them).
 """
 from __future__ import annotations
 
@@ -110,6 +111,12 @@ def load_library(path: str = LIB_PATH):
         if not os.path.exists(path):
             raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build() "
                                "or python -m paper_2505_22256_amd.build")
+        try:
+            # torch first: the library then binds to torch's HIP runtime,
+            # the one process-wide runtime (see the module docstring)
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

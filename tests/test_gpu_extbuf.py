@@ -137,3 +137,29 @@ def test_bad_external_buffers_are_refused(lbm_mod):
     g.close()
     a.free()
     b.free()
+
+
+def test_torch_tensors_as_buffers(lbm_mod):
+    """Torch tensors and a torch stream: the binding loads torch before the
+    library, so both share one HIP runtime."""
+    import torch
+    wl = W.random_small(24, nx=70, ny=45)
+    n = lbm_mod.lbm_population_bytes(wl.nx, wl.ny, lbm_mod.F32)
+    ts = [torch.empty(n, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    a = lbm_mod.Lattice(wl.nx, wl.ny, lbm_mod.F32, wl.flags, buffers=ts)
+    b = lbm_mod.Lattice(wl.nx, wl.ny, lbm_mod.F32, wl.flags)
+    stream = torch.cuda.Stream()
+    a.set_stream(stream.cuda_stream)
+    for lat in (a, b):
+        _load(lat, wl)
+    a.step(20)
+    b.step(20)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    cur = ts[a.current_buffer()].view(torch.float32).reshape(2, 9, wl.ny, wl.nx)
+    solid = torch.from_numpy(wl.solid == 1).to("cuda")
+    assert bool(torch.isnan(cur[:, :, solid]).all())
+    a.close()
+    b.close()
+    ts[0].fill_(3)
+    torch.cuda.synchronize()
+    assert int(ts[0][5].item()) == 3
