@@ -139,15 +139,20 @@ def _open_samples(wl, seed=5):
     return np.concatenate([base, edge])
 
 
+@pytest.mark.parametrize("moving", [False, True])
 @pytest.mark.parametrize("storage,tol", FULL_TOLS)
-def test_open_channel_sampled_nodes_against_oracle(oracle_mod, lbm_mod, storage, tol):
+def test_open_channel_sampled_nodes_against_oracle(oracle_mod, lbm_mod, storage, tol, moving):
     """The channel with a Zou-He inlet and an outflow instead of periodic x,
     in the launch configuration of the open-channel benchmark (default
     tile, boundary kernel instances): sampled nodes, open-edge columns
     included, advance one launch as the oracle advances their windows; a
     window that reaches an open edge carries that edge (and the inlet
-    velocities of its rows)."""
+    velocities of its rows).  With `moving`, every wall (channel walls and
+    constrictions) also slides at u_x = 0.01: the same velocity in both
+    halves, so that a window takes it whatever rows it covers."""
     wl = W.constrictions(open_ends=True)
+    if moving:
+        wl.wall_velocity = (0.01, 0.0, 0.01, 0.0)
     g = lbm_mod.lattice_from_workload(wl, storage)
     n = 2 if g.get_tile()[2] & lbm_mod.SCHED_TWO_STEP else 1
     # the dependence radius is 3 per step; at least 4, so that a window cut
@@ -168,6 +173,8 @@ def test_open_channel_sampled_nodes_against_oracle(oracle_mod, lbm_mod, storage,
         o.set_params(wl.G_c, wl.G_ads, wl.tau)
         o.set_body_accel(*wl.accel)
         o.set_inlet_velocity(wl.inlet_u[0, y0:y0 + h], wl.inlet_u[1, y0:y0 + h])
+        if moving:
+            o.set_wall_velocity(*wl.wall_velocity)
         o.set_populations(f_win)
         o.step(n)
         ref = o.get_populations()[:, :, y - y0, x - x0]
