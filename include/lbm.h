@@ -121,9 +121,12 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags);
  * e_0 = (0,0), e_1..e_4 = (1,0), (0,1), (-1,0), (0,-1), e_5..e_8 = (1,1),
  * (-1,1), (-1,-1), (1,-1); solid nodes hold all-ones bit patterns.
  * The buffer lbm_current_buffer names holds the post-collision populations
- * of the last step, f*(x, t-1) (after lbm_init_fields or lbm_set_populations
- * the state as set); the next step pulls f_i(x, t) = f*_i(x - e_i, t-1), or
- * the bounce-back at a wall link, from it.  The other buffer is scratch.
+ * of the last step, f*(x, t-1); the next step pulls f_i(x, t) =
+ * f*_i(x - e_i, t-1), or the bounce-back f*_opp(i)(x, t-1) at a wall link,
+ * from it.  After lbm_init_fields or lbm_set_populations it holds the state
+ * set, streamed backwards (f*_j(z) = f_j(z + e_j), or f_opp(j)(z) where
+ * z + e_j is solid) so that this pull returns it.  The other buffer is
+ * scratch.
  * For F32, F16 and BF16 storage the values are the deviations of the
  * storage-type comment above.  Errors: as lbm_create, and EINVAL for a null,
  * misaligned, too small, overlapping or non-device buffer. */
