@@ -42,6 +42,38 @@ STORAGES = {"f64": lbm.F64, "f32": lbm.F32, "f16": lbm.F16, "bf16": lbm.BF16}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_constrictions.json")
 
 
+def rounding_label(args) -> str:
+    if args.storage not in ("f16", "bf16"):
+        return ""
+    return " round-to-nearest-even" if args.nearest else " stochastic rounding"
+
+
+def copy_bandwidth(nbytes: int = 1 << 31, repeats: int = 5):
+    """Read+write bandwidth of a plain device copy (torch's copy kernel) of
+    `nbytes`, the best of `repeats` timed copies: what the box delivers for
+    the simplest streaming pattern, the practical ceiling beside the 8 TB/s
+    peak."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2.0 * 4 * n / (best * 1e-3) / 1e9, 1)
+
+
 def kernel_source_hash() -> str:
     """Hash of the sources that define the step kernel and its launch
     geometry (the tile is checked separately)."""
@@ -112,8 +144,8 @@ def precision_check(steps: int = 5000):
     FP64 oracle to 1e-12)."""
     wl = W.flat_drop()
     cases = [("f64", lbm.F64, 0), ("f32", lbm.F32, 0), ("f16", lbm.F16, 0),
-             ("f16_sr", lbm.F16, lbm.ROUND_STOCHASTIC), ("bf16", lbm.BF16, 0),
-             ("bf16_sr", lbm.BF16, lbm.ROUND_STOCHASTIC)]
+             ("f16_rne", lbm.F16, lbm.ROUND_NEAREST), ("bf16", lbm.BF16, 0),
+             ("bf16_rne", lbm.BF16, lbm.ROUND_NEAREST)]
     th = {}
     for name, st, fl in cases:
         g = lbm.lattice_from_workload(wl, st, fl)
@@ -139,7 +171,7 @@ def calibration_batch(args):
     import torch
     runs = W.calibration_runs()
     storage = STORAGES[args.storage]
-    flags = lbm.ROUND_STOCHASTIC if args.stochastic else 0
+    flags = lbm.ROUND_NEAREST if args.nearest else 0
     for wl in runs:
         wl.flags |= flags
     stream = torch.cuda.Stream()
@@ -166,7 +198,7 @@ def calibration_batch(args):
            "ms_per_step": round(ms / steps, 5), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if storage == lbm.F64 else "f32", "data": "synthetic",
            "config": {"workload": f"calibration batch: {len(runs)} runs, sides 128..512, flat/cylinder, "
-                                  f"seed 22256, {args.storage} storage" + (" stochastic rounding" if args.stochastic else ""),
+                                  f"seed 22256, {args.storage} storage" + rounding_label(args),
                       "runs": len(runs), "fluid_nodes": n_fluid,
                       "tile": {"block": tile[0], "seg_rows": tile[1], "sched": tile[2]},
                       "graph_steps": 50}}
@@ -209,8 +241,8 @@ def porous_precision(args):
     steps = args.steps if args.steps_given else wl.steps
     every = args.record_every
     cases = [("f64", lbm.F64, 0), ("f32", lbm.F32, 0), ("f16", lbm.F16, 0),
-             ("f16_sr", lbm.F16, lbm.ROUND_STOCHASTIC), ("bf16", lbm.BF16, 0),
-             ("bf16_sr", lbm.BF16, lbm.ROUND_STOCHASTIC)]
+             ("f16_rne", lbm.F16, lbm.ROUND_NEAREST), ("bf16", lbm.BF16, 0),
+             ("bf16_rne", lbm.BF16, lbm.ROUND_NEAREST)]
     hist, rate = {}, {}
     stream = torch.cuda.Stream()
     for name, st, fl in cases:
@@ -257,8 +289,8 @@ def cylinder_sweep(args):
     with open(os.path.join(ROOT, "tests", "golden", "cylinder_theta.json")) as f:
         ref = json.load(f)
     cases = [("f64", lbm.F64, 0), ("f32", lbm.F32, 0), ("f16", lbm.F16, 0),
-             ("f16_sr", lbm.F16, lbm.ROUND_STOCHASTIC), ("bf16", lbm.BF16, 0),
-             ("bf16_sr", lbm.BF16, lbm.ROUND_STOCHASTIC)]
+             ("f16_rne", lbm.F16, lbm.ROUND_NEAREST), ("bf16", lbm.BF16, 0),
+             ("bf16_rne", lbm.BF16, lbm.ROUND_NEAREST)]
     rows = []
     for c in ref["cases"]:
         wl = W.cylinder_drop(G_ads=c["G_ads"])
@@ -449,10 +481,11 @@ def obstacle_flow(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=7000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGES))
-    ap.add_argument("--stochastic", action="store_true", help="stochastic rounding (f16/bf16)")
+    ap.add_argument("--nearest", action="store_true",
+                    help="f16/bf16: round-to-nearest-even stores instead of the default stochastic rounding")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--tile", default="default",
                     help="default (the library's measured default for the storage), auto (autotune on the "
@@ -518,7 +551,7 @@ def main():
 
     wl = W.constrictions()
     storage = STORAGES[args.storage]
-    flags = lbm.ROUND_STOCHASTIC if args.stochastic else 0
+    flags = lbm.ROUND_NEAREST if args.nearest else 0
     stream = torch.cuda.Stream()
     lat = lbm.lattice_from_workload(wl, storage, flags)
     lat.set_stream(stream.cuda_stream)
@@ -534,25 +567,36 @@ def main():
     n_fluid = lat.fluid_nodes
     bpu = lat.bytes_per_update
 
+    # the K timed steps run as 5 equal repeats (the last takes the
+    # remainder), each bracketed by HIP events on the library's stream; the
+    # step rate is the median repeat's
+    reps = 5 if args.steps >= 10 else 1
+    chunk = [args.steps // reps] * reps
+    chunk[-1] += args.steps - sum(chunk)
     with torch.cuda.stream(stream):
         lat.step(args.warmup)
         lat.synchronize()
         torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        lat.step(args.steps)
-        ev1.record(stream)
-        ev1.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        evs[0].record(stream)
+        for r in range(reps):
+            lat.step(chunk[r])
+            evs[r + 1].record(stream)
+        evs[-1].synchronize()
         torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    ms = evs[0].elapsed_time(evs[-1])
+    rep_ms_step = [evs[r].elapsed_time(evs[r + 1]) / chunk[r] for r in range(reps)]
     diag, t_diag = lat.get_diag() if args.diag_every > 0 else (None, None)
-    ms_step = ms / args.steps
-    mlups = n_fluid * args.steps / (ms * 1e-3) / 1e6
+    ms_step = float(np.median(rep_ms_step))
+    mlups = n_fluid / (ms_step * 1e-3) / 1e6
     achieved = bpu * n_fluid / (ms_step * 1e-3) / 1e9
-    traffic = measured_traffic(args.storage + ("_sr" if args.stochastic else ""), (block, rows, sched))
+    traffic = measured_traffic(args.storage + ("_rne" if args.nearest else ""), (block, rows, sched))
     steps_per_launch = 2 if (sched & lbm.SCHED_TWO_STEP) and storage != lbm.F64 else 1
     lat.close()
+    copy_gbs = copy_bandwidth()
+    # real HBM rate of the step kernel: counter bytes per launch over the
+    # measured time per launch (only while the counters match the kernel)
+    hbm_gbs = traffic / (steps_per_launch * ms_step * 1e-3) / 1e9 if traffic else None
 
     out = {
         "metric": METRIC,
@@ -569,7 +613,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"constrictions {wl.nx}x{wl.ny} (64 squares of side 128, seed 355), "
                                f"G_c=0.9 G_ads=0.15 tau=1 g=2e-6, {args.storage} storage"
-                               + (" stochastic rounding" if args.stochastic else ""),
+                               + rounding_label(args),
                    "nx": wl.nx, "ny": wl.ny, "fluid_nodes": n_fluid, "storage": args.storage,
                    "tile": {"block": block, "seg_rows": rows, "sched": sched},
                    "diag_every": args.diag_every},
@@ -577,7 +621,12 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_update": bpu, "steps_per_launch": steps_per_launch,
                      "hbm_bytes_per_update": (round(traffic / (steps_per_launch * n_fluid), 1)
-                                              if traffic else None)},
+                                              if traffic else None),
+                     "hbm_measured_gbs": round(hbm_gbs, 1) if hbm_gbs else None,
+                     "hbm_measured_frac": round(hbm_gbs / HBM_PEAK_GBS, 4) if hbm_gbs else None,
+                     "copy_gbs": copy_gbs, "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "repeats_ms_per_step": [round(v, 5) for v in rep_ms_step],
+        "timed_ms_total": round(ms, 2),
     }
     if diag is not None:
         out["diagnostics"] = {"t": t_diag, "mass1": diag[0], "mass2": diag[1], "max_u": diag[4],

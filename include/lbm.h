@@ -55,8 +55,9 @@ enum {
 
 /* Population storage.  F64 stores f and computes in FP64.  F32, F16 and
  * BF16 store the deviation g_i = f_i - w_i rho0_k (rho0_k = mean initial
- * density of component k over fluid nodes), rounded to nearest even, and
- * compute in FP32. */
+ * density of component k over fluid nodes) and compute in FP32.  F32
+ * rounds to nearest even; F16 and BF16 round stochastically unless
+ * LBM_ROUND_NEAREST is given (see the flags below). */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
 
 /* Context flags.  PERIODIC_* wrap an axis; along a non-periodic axis the
@@ -80,12 +81,17 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
  *   edge reads its ghost, the node of the same row clamped into the domain
  *   (zero when that is solid), and a second-layer one takes the Table 1
  *   copy; the solid switch s of Eq. 9 there is the ghost's.
- * ROUND_STOCHASTIC (F16 and BF16 storage only; ignored otherwise) rounds the
- * stored deviation up or down with probability proportional to the
- * distance, from a counter-based hash of (node, component, direction,
- * step): unbiased, reproducible and independent of the tiling.  The default
- * is round-to-nearest-even, whose error repeats every step in a steady
- * state and accumulates (mass drift). */
+ * Rounding of F16 and BF16 stores (ignored for F64 and F32):
+ *   ROUND_STOCHASTIC (the default for F16 and BF16; giving it is allowed)
+ *            rounds the stored deviation up or down with probability
+ *            proportional to the distance, from a counter-based hash of
+ *            (node, component, direction, step): unbiased, reproducible
+ *            and independent of the tiling.
+ *   ROUND_NEAREST  round-to-nearest-even instead.  Its error repeats every
+ *            step in a steady state and accumulates (mass drift): on the
+ *            flat-wall droplet the contact angle is off by about 5 degrees
+ *            (F16) and 11 degrees (BF16) after 5000 steps.
+ *   Both together are EINVAL.  lbm_get_flags returns the flags in effect. */
 enum {
     LBM_PERIODIC_X = 1,
     LBM_PERIODIC_Y = 2,
@@ -96,7 +102,8 @@ enum {
     LBM_FORCE_DENSITY = 64,
     LBM_ROUND_STOCHASTIC = 128,
     LBM_INLET = 256,
-    LBM_OUTFLOW = 512
+    LBM_OUTFLOW = 512,
+    LBM_ROUND_NEAREST = 1024
 };
 
 /* Tile schedule bits for lbm_set_tile. */
@@ -106,7 +113,7 @@ enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2, LBM_SCHED_XCD_SLABS = 4, LBM_SC
 enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
 
 /* Create a context on the current HIP device.  nx, ny >= 5; storage one of
- * LBM_F64..LBM_BF16; flags a combination of LBM_PERIODIC_X..LBM_OUTFLOW.
+ * LBM_F64..LBM_BF16; flags a combination of LBM_PERIODIC_X..LBM_ROUND_NEAREST.
  * Allocates two population buffers of 18*nx*ny elements (ping-pong).
  * Errors: EINVAL (sizes, storage, flags), ENOMEM, EDEVICE (no gfx950 GPU). */
 int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags);
@@ -126,7 +133,10 @@ int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags);
  * from it.  After lbm_init_fields or lbm_set_populations it holds the state
  * set, streamed backwards (f*_j(z) = f_j(z + e_j), or f_opp(j)(z) where
  * z + e_j is solid) so that this pull returns it.  The other buffer is
- * scratch.
+ * the next step's output: the step overwrites every fluid-node slot of it,
+ * so a caller may use those in between, but it writes no solid-node slot
+ * (they keep the all-ones pattern that marks solid nodes to the step after
+ * it); a caller must leave those slots, in either buffer, unchanged.
  * For F32, F16 and BF16 storage the values are the deviations of the
  * storage-type comment above.  Errors: as lbm_create, and EINVAL for a null,
  * misaligned, too small, overlapping or non-device buffer. */
@@ -137,6 +147,11 @@ int lbm_create_ex(lbm_ctx **out, int nx, int ny, int storage, unsigned flags, vo
 size_t lbm_population_bytes(int nx, int ny, int storage);
 /* 0 for buf_a, 1 for buf_b: the buffer that holds the current state. */
 int lbm_current_buffer(const lbm_ctx *c);
+/* Flags in effect: those given at creation with the storage's rounding
+ * resolved (LBM_ROUND_STOCHASTIC set for F16 and BF16 unless
+ * LBM_ROUND_NEAREST was given; neither bit for F64 and F32).  0 for a null
+ * context. */
+unsigned lbm_get_flags(const lbm_ctx *c);
 
 /* Solid mask, ny*nx bytes, 0 = fluid, non-zero = solid (the switch s(x) of
  * Eq. 9).  Copied.  Invalidates the populations (init again). */
@@ -169,8 +184,11 @@ int lbm_set_wall_velocity(lbm_ctx *c, double ubx, double uby, double utx, double
  * Sec. 3.3.  Default zero.  EINVAL if a value is non-finite or ux >= 1. */
 int lbm_set_inlet_velocity(lbm_ctx *c, const double *ux, const double *uy);
 
-/* Initial densities (ny*nx each, FP64): f_i = w_i rho_k, u = 0, t = 0.
- * Solid entries are ignored.  EINVAL on a non-finite fluid density. */
+/* Initial densities (ny*nx each, FP64): f_i = w_i rho_k, u = 0, t = 0,
+ * i.e. the equilibrium of Eq. 6 at rest (the paper starts from the two
+ * phases' densities without stating the populations).  Solid entries are
+ * ignored.  EINVAL on a non-finite fluid density, ESTATE before
+ * lbm_set_geometry. */
 int lbm_init_fields(lbm_ctx *c, const double *rho1, const double *rho2);
 
 /* Pre-collision populations f(x, t) as [2][9][ny][nx] FP64; solid entries
@@ -186,9 +204,14 @@ int lbm_get_populations(lbm_ctx *c, double *f);
  * w, h < 1.  Synchronous. */
 int lbm_get_populations_window(lbm_ctx *c, int x0, int y0, int w, int h, double *f);
 
-/* Advance n >= 0 time steps (collide, then stream).  Asynchronous: the
- * kernels are enqueued on the context stream.  ESTATE before geometry,
- * parameters and initial fields. */
+/* Advance n >= 0 time steps of Eq. 1: densities and momenta (Eq. 3-4),
+ * cohesion on the E8 stencil with the Table 1 second-layer copy (Eq. 8,
+ * Sec. 2.4), adhesion with the local G of component 1 (Eq. 9-12), body
+ * force, the Guo-shifted velocity (Eq. 5), BGK collision with the Guo
+ * forcing term (Eq. 2, 6, 7), then pull streaming with halfway bounce-back
+ * (Sec. 3.1-3.2).  Asynchronous: the kernels are enqueued on the context
+ * stream.  ESTATE before geometry, parameters and initial fields; EINVAL
+ * for n < 0; EDEVICE when a launch fails. */
 int lbm_step(lbm_ctx *c, int n);
 
 /* Fused diagnostics: with every > 0, every step whose start time t is a
@@ -213,7 +236,11 @@ int lbm_get_fields(lbm_ctx *c, double *rho1, double *rho2, double *ux, double *u
 /* Whole-lattice diagnostics at the current time, FP64 with a deterministic
  * compensated two-pass sum: out = {M1, M2, Px, Py, max|u|, min rho1,
  * max rho1, number of fluid nodes with a non-finite rho or u}, where
- * M_k = sum rho_k and P = sum (rho_1 + rho_2) u^eq over fluid nodes. */
+ * M_k = sum rho_k (Eq. 3; conserved by Eq. 1-2) and P = sum (rho_1 +
+ * rho_2) u^eq with u^eq of Eq. 5 (the spurious-current measure of Sec. 3.2
+ * is max|u|).  Fluid nodes only; a node with a non-finite value is counted
+ * in out[7] and left out of the rest.  With no fluid node, min and max
+ * rho1 are 0.  Synchronous; ESTATE before initialisation. */
 int lbm_reduce(lbm_ctx *c, double out[8]);
 
 /* Static contact angle (degrees, measured through component 1).  Interface
@@ -226,7 +253,9 @@ int lbm_reduce(lbm_ctx *c, double out[8]);
  * EUNSTABLE if fewer than 3 points remain or the fit fails. */
 int lbm_contact_angle(lbm_ctx *c, int wall_kind, const double wall[3], double *theta_deg);
 
-/* Tables the step kernel derives from the geometry, for checking:
+/* Tables the step kernel derives from the geometry (Sec. 2.3-2.4: the
+ * bounce-back links of halfway bounce-back, and the E8 stencil positions
+ * after the Table 1 second-layer rule), for checking:
  *   link[ny*nx]: bit i-1 set when the pull source x - e_i of fluid node x is
  *     unavailable (bounce-back); 0 on solid nodes;
  *   nw_list[n_nw]: fluid nodes with an unavailable E8 stencil position,
@@ -312,8 +341,9 @@ typedef struct {
  * Each run's result is bitwise that of a single context with the same
  * inputs and tile shape. */
 int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int storage);
-/* (LBM_ROUND_STOCHASTIC must be set on all runs of a batch or on none:
- * LBM_EINVAL otherwise.) */
+/* (The rounding of F16 and BF16 stores is a property of the launch: every
+ * run of a batch must resolve to the same mode, i.e. LBM_ROUND_NEAREST on
+ * all runs or on none; LBM_EINVAL otherwise.) */
 int lbm_batch_set_tile(lbm_batch *b, int block, int seg_rows);
 /* Tile of the batched kernel by measurement: times the current tile and
  * then block in {64, 128, 256} x seg_rows in {8, 16, 24, 32, 48, 64, 128,

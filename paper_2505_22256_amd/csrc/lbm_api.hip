@@ -305,6 +305,8 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     if (storage < LBM_F64 || storage > LBM_BF16) return LBM_EINVAL;
     if (flags & ~(unsigned)FL_ALL) return LBM_EINVAL;
     if ((flags & (LBM_INLET | LBM_OUTFLOW)) && (flags & LBM_PERIODIC_X)) return LBM_EINVAL;
+    if ((flags & LBM_ROUND_STOCHASTIC) && (flags & LBM_ROUND_NEAREST)) return LBM_EINVAL;
+    flags = resolve_rounding(flags, storage);
     // one component's 9 direction arrays are addressed through a 32-bit range
     if ((long long)nx * ny * 9 * (long long)elem_size(storage) >= (1LL << 32)) return LBM_EINVAL;
     int ndev = 0;
@@ -420,6 +422,8 @@ int lbm_current_buffer(const lbm_ctx *c)
     if (!c) return LBM_EINVAL;
     return c->cur;
 }
+
+unsigned lbm_get_flags(const lbm_ctx *c) { return c ? c->flags : 0u; }
 
 void lbm_destroy(lbm_ctx *c)
 {

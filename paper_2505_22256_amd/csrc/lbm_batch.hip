@@ -362,14 +362,17 @@ int lbm_batch_create(lbm_batch **out, int nruns, const lbm_run_desc *runs, int s
             delete b;
             return LBM_EINVAL;
         }
-        // stochastic rounding is a property of the launch: all runs or none
-        if (r > 0 && (d.flags & LBM_ROUND_STOCHASTIC) != (runs[0].flags & LBM_ROUND_STOCHASTIC)) {
+        // the rounding of 16-bit stores is a property of the launch: every
+        // run must resolve to the same mode
+        const unsigned rmask = LBM_ROUND_STOCHASTIC | LBM_ROUND_NEAREST;
+        if (((d.flags & rmask) == rmask) ||
+            (r > 0 && (resolve_rounding(d.flags, storage) & rmask) != (resolve_rounding(runs[0].flags, storage) & rmask))) {
             delete b;
             return LBM_EINVAL;
         }
         br.nx = d.nx;
         br.ny = d.ny;
-        br.flags = d.flags;
+        br.flags = resolve_rounding(d.flags, storage);
         br.Gc = d.G_c;
         br.Gw2 = d.G_c;
         br.Gw1 = d.G_c + 2.0 * d.G_ads;

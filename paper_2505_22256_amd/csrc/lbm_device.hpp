@@ -28,7 +28,8 @@ enum : unsigned {
     FL_ROUND_STOCHASTIC = 128u,
     FL_INLET = 256u,    // Zou-He velocity inlet at x = 0 (Sec. 3.3)
     FL_OUTFLOW = 512u,  // zero-gradient outflow at x = nx - 1 (Sec. 3.3)
-    FL_ALL = 1023u
+    FL_ROUND_NEAREST = 1024u,  // 16-bit storage rounds to nearest even (resolved on the host)
+    FL_ALL = 2047u
 };
 
 // Kernel modes (bit set).

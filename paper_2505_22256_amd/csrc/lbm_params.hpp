@@ -14,6 +14,18 @@ using lbm::qw;
 // Schedule bits of a tile (lbm_set_tile).
 enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u, SCHED_XCD_SLABS = 4u, SCHED_TWO_STEP = 8u };
 
+// Rounding of the stores in effect for a storage type: F16 and BF16 round
+// stochastically unless LBM_ROUND_NEAREST asks for round-to-nearest-even;
+// F64 and F32 carry neither bit.
+inline unsigned resolve_rounding(unsigned flags, int storage)
+{
+    const bool narrow = storage == LBM_F16 || storage == LBM_BF16;
+    flags &= ~(unsigned)LBM_ROUND_STOCHASTIC;
+    if (narrow && !(flags & LBM_ROUND_NEAREST)) flags |= LBM_ROUND_STOCHASTIC;
+    if (!narrow) flags &= ~(unsigned)LBM_ROUND_NEAREST;
+    return flags;
+}
+
 // Strips are block - 4 columns wide (balanced over nx), or, with
 // SCHED_ALIGN, the widest multiple of `align_cols` columns that fits, from
 // x = 0, so that every strip's stores start on a 128-byte boundary.

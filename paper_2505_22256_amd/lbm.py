@@ -33,6 +33,7 @@ PERIODIC_X, PERIODIC_Y = 1, 2
 SCHEME_ORIGINAL, E8_COPY_OFF, WALLPSI_SELF, VEL_LITERAL, FORCE_DENSITY = 4, 8, 16, 32, 64
 ROUND_STOCHASTIC = 128
 INLET, OUTFLOW = 256, 512
+ROUND_NEAREST = 1024
 WALL_FLAT, WALL_CYLINDER = 0, 1
 SCHED_ALIGN, SCHED_BANDS, SCHED_XCD_SLABS, SCHED_TWO_STEP = 1, 2, 4, 8
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
@@ -56,6 +57,7 @@ SIGNATURES = {
     "lbm_create_ex": (_I, [ctypes.POINTER(_P), _I, _I, _I, _U, _P, _P, ctypes.c_size_t]),
     "lbm_population_bytes": (ctypes.c_size_t, [_I, _I, _I]),
     "lbm_current_buffer": (_I, [_P]),
+    "lbm_get_flags": (_U, [_P]),
     "lbm_set_geometry": (_I, [_P, _P]),
     "lbm_set_params": (_I, [_P, _D, _D, _D]),
     "lbm_set_adhesion": (_I, [_P, _D, _D, _D]),
@@ -161,8 +163,18 @@ def lbm_population_bytes(nx: int, ny: int, storage: int) -> int:
 def _device_span(t):
     """(address, bytes) of a device array given as an object with
     data_ptr() (a torch tensor; its bytes are numel * element_size) or as an
-    (address, bytes) pair."""
+    (address, bytes) pair.  A tensor must be contiguous and lie on the
+    current HIP device: the library treats the span as one contiguous
+    buffer of that device."""
     if hasattr(t, "data_ptr"):
+        if hasattr(t, "is_contiguous") and not t.is_contiguous():
+            raise ValueError("population buffer must be a contiguous tensor")
+        dev = getattr(t, "device", None)
+        if dev is not None:
+            import torch
+            if dev.type != "cuda" or dev.index != torch.cuda.current_device():
+                raise ValueError(f"population buffer lies on {dev}, not on the current HIP device "
+                                 f"cuda:{torch.cuda.current_device()}")
         return int(t.data_ptr()), int(t.numel() * t.element_size())
     a, n = t
     return int(a), int(n)
@@ -199,6 +211,10 @@ class Lattice:
             self.h = lbm_create_ex(nx, ny, storage, flags, pa, pb, min(na, nb))
             self._ext = tuple(buffers)
         self.nx, self.ny, self.storage, self.flags = nx, ny, storage, flags
+
+    def flags_in_effect(self) -> int:
+        """Creation flags with the storage's rounding resolved (lbm_get_flags)."""
+        return int(self._L.lbm_get_flags(self.h))
 
     def close(self):
         if getattr(self, "h", None):

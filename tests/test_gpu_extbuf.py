@@ -163,3 +163,49 @@ def test_torch_tensors_as_buffers(lbm_mod):
     ts[0].fill_(3)
     torch.cuda.synchronize()
     assert int(ts[0][5].item()) == 3
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_fluid_slots_of_the_other_buffer_are_overwritten(lbm_mod, storage):
+    """The buffer that lbm_current_buffer does not name is the next step's
+    output: overwriting its fluid-node slots with garbage between steps
+    (solid-node slots left as the library wrote them) changes nothing,
+    because the step writes every fluid slot before any step reads it."""
+    import torch
+    wl = W.random_small(25, nx=70, ny=45)
+    n = lbm_mod.lbm_population_bytes(wl.nx, wl.ny, storage)
+    ts = [torch.empty(n, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    a = lbm_mod.Lattice(wl.nx, wl.ny, storage, wl.flags, buffers=ts)
+    b = lbm_mod.Lattice(wl.nx, wl.ny, storage, wl.flags)
+    for lat in (a, b):
+        _load(lat, wl)
+        lat.set_tile(64, 8, 8)
+    dt = torch.float32 if storage == 1 else torch.int16
+    fluid = torch.from_numpy(wl.solid == 0).to("cuda")
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    for k in (1, 2, 3, 10):
+        a.synchronize()
+        other = ts[a.current_buffer() ^ 1].view(dt).reshape(2, 9, wl.ny, wl.nx)
+        junk = torch.randint(-30000, 30000, other.shape, generator=gen, device="cuda").to(dt)
+        other[:, :, fluid] = junk[:, :, fluid]
+        torch.cuda.synchronize()
+        a.step(k)
+        b.step(k)
+        assert np.array_equal(a.get_populations(), b.get_populations()), k
+    a.close()
+    b.close()
+
+
+def test_binding_refuses_strided_or_foreign_tensors(lbm_mod):
+    """The binding hands the library one contiguous span per buffer: a
+    strided view or a host tensor is refused before the library sees it."""
+    import torch
+    wl = W.random_small(26, nx=30, ny=20)
+    n = lbm_mod.lbm_population_bytes(wl.nx, wl.ny, lbm_mod.F32)
+    big = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
+    good = torch.empty(n, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        lbm_mod.Lattice(wl.nx, wl.ny, lbm_mod.F32, wl.flags, buffers=[big[::2], good])
+    with pytest.raises(ValueError):
+        lbm_mod.Lattice(wl.nx, wl.ny, lbm_mod.F32, wl.flags,
+                        buffers=[torch.empty(n, dtype=torch.uint8), good])

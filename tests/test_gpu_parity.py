@@ -23,7 +23,7 @@ REL64 = 1e-12
 def _pair(oracle_mod, lbm_mod, wl, storage, flags_extra=0, pops=None, tile=None, adhesion=None):
     # stochastic rounding concerns reduced-precision storage only; the FP64
     # oracle has no such flag
-    o = oracle_mod.Oracle(wl.nx, wl.ny, (wl.flags | flags_extra) & ~lbm_mod.ROUND_STOCHASTIC)
+    o = oracle_mod.Oracle(wl.nx, wl.ny, (wl.flags | flags_extra) & ~(lbm_mod.ROUND_STOCHASTIC | lbm_mod.ROUND_NEAREST))
     g = lbm_mod.Lattice(wl.nx, wl.ny, storage, wl.flags | flags_extra)
     for s in (o, g):
         s.set_geometry(wl.solid)
@@ -72,6 +72,43 @@ def test_fp64_random_geometry_random_populations(oracle_mod, lbm_mod, seed, extr
     o.step(200)
     g.step(200)
     assert _relmax(g.get_populations(), o.get_populations()) < REL64
+
+
+def _speckled(seed, nx, ny, flags, frac=0.25):
+    """Random masks with a quarter of the nodes solid, placed one by one:
+    most solid features are a single voxel thick, so second-layer stencil
+    positions often lie just beyond a one-node wall (Sec. 2.4, Table 1:
+    the copy then takes the first-layer value on the near side), and
+    fluid nodes enclosed on several sides are common."""
+    rng = np.random.default_rng(seed)
+    solid = (rng.random((ny, nx)) < frac).astype(np.uint8)
+    y, x = np.mgrid[0:ny, 0:nx]
+    inside = (x - nx * rng.uniform(0.3, 0.7)) ** 2 + (y - ny * rng.uniform(0.3, 0.7)) ** 2 < (min(nx, ny) / 3) ** 2
+    rho1 = np.where(solid != 0, 0.0, np.where(inside, 1.0, 0.03))
+    rho2 = np.where(solid != 0, 0.0, np.where(inside, 0.03, 1.0))
+    return W.Workload("speckled", nx, ny, flags, solid, rho1, rho2, G_c=0.9,
+                      G_ads=float(rng.uniform(-0.3, 0.3)), tau=float(rng.uniform(0.8, 1.2)),
+                      accel=(1e-5, -2e-5, -1e-5, 3e-5), steps=200)
+
+
+@pytest.mark.parametrize("seed,periodic", [(0, 3), (1, 1), (2, 0), (3, 2)])
+@pytest.mark.parametrize("extra", [0, 8, 16])
+def test_fp64_one_voxel_features(oracle_mod, lbm_mod, seed, periodic, extra):
+    """Dynamics on speckled masks (one-voxel-thick solids everywhere), from
+    random populations, with the Table 1 copy, without it (E8_COPY_OFF) and
+    with WALLPSI_SELF: 200 steps of the device against the oracle at 1e-12
+    (two tiles, so strip and segment edges cut through the speckle)."""
+    wl = _speckled(700 + seed, 37 + 3 * seed, 29 + 2 * seed, periodic)
+    f0 = W.random_populations(710 + seed, wl, amplitude=0.1)
+    ref = None
+    for tile in ((64, 5), (128, 16)):
+        o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, flags_extra=extra, pops=f0, tile=tile)
+        if ref is None:
+            o.step(200)
+            ref = o.get_populations()
+            assert np.all(np.isfinite(ref))
+        g.step(200)
+        assert _relmax(g.get_populations(), ref) < REL64, tile
 
 
 def test_fp64_multitile_ragged_nonperiodic(oracle_mod, lbm_mod):
@@ -202,13 +239,14 @@ def test_fp32_flat_drop_density(oracle_mod, lbm_mod):
         assert np.max(np.abs(go[k] - ro[k])) <= 1e-4 * np.max(np.abs(ro[k]))
 
 
-@pytest.mark.parametrize("storage,flags,tol", [(1, 0, 0.5), (2, 128, 1.0), (3, 128, 1.0)])
+@pytest.mark.parametrize("storage,flags,tol", [(1, 0, 0.5), (2, 0, 1.0), (3, 0, 1.0), (2, 128, 1.0)])
 def test_reduced_storage_contact_angle(oracle_mod, lbm_mod, storage, flags, tol):
     """Flat-wall droplet after 5000 steps: contact angle against the FP64
     oracle, 0.5 degree for FP32 storage and 1 degree for FP16 / BF16
-    storage with stochastic rounding.  (With round-to-nearest-even the
-    FP16 / BF16 runs miss by 5 / 11 degrees: the rounding error of a steady
-    state repeats every step and drains mass; see the next test.)"""
+    storage in their default rounding (stochastic; giving the flag
+    explicitly is the same).  (With LBM_ROUND_NEAREST the FP16 / BF16 runs
+    miss by 5 / 11 degrees: the rounding error of a steady state repeats
+    every step and drains mass; see the next test.)"""
     wl = W.flat_drop()
     o, g = _pair(oracle_mod, lbm_mod, wl, storage, flags_extra=flags)
     o.step(5000)
@@ -235,13 +273,31 @@ def test_stochastic_rounding_removes_mass_drift(oracle_mod, lbm_mod, storage, bo
     o.init_fields(wl.rho1, wl.rho2)
     m0 = o.reduce()[:2]
     drift = {}
-    for fl in (0, lbm_mod.ROUND_STOCHASTIC):
+    for fl in (lbm_mod.ROUND_NEAREST, 0):
         g = lbm_mod.lattice_from_workload(wl, storage, fl)
+        assert bool(g.flags_in_effect() & lbm_mod.ROUND_STOCHASTIC) == (fl == 0)
         g.step(3000)
         m = g.reduce()[:2]
         drift[fl] = np.max(np.abs(m - m0) / m0)
-    assert drift[lbm_mod.ROUND_STOCHASTIC] < 0.25 * drift[0], drift
-    assert drift[lbm_mod.ROUND_STOCHASTIC] < bound, drift
+    assert drift[0] < 0.25 * drift[lbm_mod.ROUND_NEAREST], drift
+    assert drift[0] < bound, drift
+
+
+def test_rounding_flags_in_effect(lbm_mod):
+    """16-bit storage rounds stochastically unless LBM_ROUND_NEAREST is
+    given; FP32 and FP64 carry neither bit; both bits together are
+    refused."""
+    SR, RNE = lbm_mod.ROUND_STOCHASTIC, lbm_mod.ROUND_NEAREST
+    want = {(lbm_mod.F16, 0): SR, (lbm_mod.BF16, 0): SR, (lbm_mod.F16, SR): SR, (lbm_mod.BF16, RNE): RNE,
+            (lbm_mod.F32, 0): 0, (lbm_mod.F32, SR): 0, (lbm_mod.F64, RNE): 0}
+    for (storage, fl), bits in want.items():
+        g = lbm_mod.Lattice(16, 12, storage, 3 | fl)
+        assert g.flags_in_effect() & (SR | RNE) == bits, (storage, fl)
+        assert g.flags_in_effect() & 3 == 3
+        g.close()
+    for storage in (lbm_mod.F16, lbm_mod.F32):
+        with pytest.raises(lbm_mod.LbmError):
+            lbm_mod.Lattice(16, 12, storage, SR | RNE)
 
 
 def test_checkpoint_resume_is_bitwise(lbm_mod, tmp_path):

@@ -22,7 +22,7 @@ def _cases():
             W.cylinder_drop(G_ads=0.2, nx=96, ny=90, R=14, centre=(48, 34), r_drop=18, drop_centre=(48, 60))]
 
 
-@pytest.mark.parametrize("storage,flags", [(1, 0), (2, 0), (2, 128), (3, 128)])
+@pytest.mark.parametrize("storage,flags", [(1, 0), (2, 0), (2, 1024), (3, 0), (3, 1024)])
 def test_two_step_is_bitwise_one_step(lbm_mod, storage, flags):
     tiles = [(128, 16, TWO), (64, 8, TWO | 2), (128, 0, TWO), (128, 32, TWO | 3), (64, 0, TWO | 4),
              (256, 24, TWO | 2), (256, 0, TWO)]
