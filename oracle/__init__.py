@@ -16,6 +16,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
+SRC3 = os.path.join(HERE, "lbm_oracle3d.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 OK, EINVAL, ESTATE, ENOMEM, EUNSTABLE = 0, -1, -2, -3, -5
@@ -25,12 +26,15 @@ INLET, OUTFLOW = 256, 512
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain -O2: no FMA contraction on x86-64)."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+    """Compile liboracle.so (2-D and 3-D oracles) with gcc (plain -O2: no
+    FMA contraction on x86-64)."""
+    srcs = [SRC, SRC3]
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
+            os.path.getmtime(f) for f in srcs + [SRC[:-1] + "h", SRC3[:-1] + "h"]):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
-           "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp, SRC, "-lm"]
+           "-Wall", "-Wextra", "-Wno-unused-parameter", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
@@ -76,6 +80,29 @@ def lib():
             "oracle_circle_fit": (I, [P, P, I, P]),
             "oracle_threads": (I, []),
             "oracle_set_threads": (I, [I]),
+            "oracle3d_create": (I, [ctypes.POINTER(P), I, I, I, U]),
+            "oracle3d_destroy": (None, [P]),
+            "oracle3d_last_error": (ctypes.c_char_p, [P]),
+            "oracle3d_set_geometry": (I, [P, P]),
+            "oracle3d_set_params": (I, [P, D, D, D]),
+            "oracle3d_set_adhesion": (I, [P, D, D, D]),
+            "oracle3d_set_body_accel": (I, [P, P]),
+            "oracle3d_init_fields": (I, [P, P, P]),
+            "oracle3d_set_populations": (I, [P, P]),
+            "oracle3d_get_populations": (I, [P, P]),
+            "oracle3d_step": (I, [P, I]),
+            "oracle3d_time": (ctypes.c_long, [P]),
+            "oracle3d_get_fields": (I, [P, P, P, P, P, P]),
+            "oracle3d_reduce": (I, [P, P]),
+            "oracle3d_node_forces": (I, [P, I, I, I, P]),
+            "oracle3d_adhesion_vector": (I, [P, I, I, I, P]),
+            "oracle3d_d3q19": (None, [P, P, P, P, P]),
+            "oracle3d_stencil": (I, [P, P, P, P, P]),
+            "oracle3d_equilibrium": (None, [D, P, P]),
+            "oracle3d_forcing": (None, [P, P, P]),
+            "oracle3d_interface_points": (I, [P, I, P, P, P, P, I, ctypes.POINTER(I)]),
+            "oracle3d_sphere_fit": (I, [P, P, P, I, P]),
+            "oracle3d_contact_angle": (I, [P, I, P, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -263,3 +290,148 @@ def set_threads(n):
     """Threads of the oracle's row loops (results are independent of it);
     returns the previous count."""
     return lib().oracle_set_threads(int(n))
+
+
+# ---------------------------------------------------------------------------
+# Three dimensions (Sec. 3.5): D3Q19 and the 92-position 3-D stencil
+# ---------------------------------------------------------------------------
+PERIODIC_Z = 2048
+
+
+class Oracle3D:
+    """ctypes wrapper around one 3-D oracle context.  Arrays are [nz, ny, nx];
+    populations [2, 19, nz, ny, nx]."""
+
+    def __init__(self, nx: int, ny: int, nz: int, flags: int = 0):
+        self._L = lib()
+        h = ctypes.c_void_p()
+        rc = self._L.oracle3d_create(ctypes.byref(h), nx, ny, nz, flags)
+        if rc:
+            raise OracleError(rc, "create failed")
+        self.h, self.nx, self.ny, self.nz, self.flags = h, nx, ny, nz, flags
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self._L.oracle3d_destroy(self.h)
+            self.h = None
+
+    def _chk(self, rc):
+        if rc:
+            raise OracleError(rc, self._L.oracle3d_last_error(self.h).decode())
+        return rc
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def set_geometry(self, solid):
+        s = np.ascontiguousarray(solid, dtype=np.uint8).reshape(self.shape)
+        self._solid = s
+        self._chk(self._L.oracle3d_set_geometry(self.h, _ptr(s)))
+
+    def set_params(self, G_c, G_ads, tau):
+        self._chk(self._L.oracle3d_set_params(self.h, G_c, G_ads, tau))
+
+    def set_adhesion(self, G_w1, G_w2, delta=0.8):
+        self._chk(self._L.oracle3d_set_adhesion(self.h, G_w1, G_w2, delta))
+
+    def set_body_accel(self, g):
+        a = np.ascontiguousarray(g, dtype=np.float64).reshape(6)
+        self._chk(self._L.oracle3d_set_body_accel(self.h, _ptr(a)))
+
+    def init_fields(self, rho1, rho2):
+        r1 = np.ascontiguousarray(rho1, dtype=np.float64).reshape(self.shape)
+        r2 = np.ascontiguousarray(rho2, dtype=np.float64).reshape(self.shape)
+        self._chk(self._L.oracle3d_init_fields(self.h, _ptr(r1), _ptr(r2)))
+
+    def set_populations(self, f):
+        a = np.ascontiguousarray(f, dtype=np.float64).reshape((2, 19) + self.shape)
+        self._chk(self._L.oracle3d_set_populations(self.h, _ptr(a)))
+
+    def get_populations(self):
+        a = np.empty((2, 19) + self.shape)
+        self._chk(self._L.oracle3d_get_populations(self.h, _ptr(a)))
+        return a
+
+    def step(self, n=1):
+        self._chk(self._L.oracle3d_step(self.h, int(n)))
+
+    @property
+    def time(self):
+        return self._L.oracle3d_time(self.h)
+
+    def get_fields(self):
+        out = [np.empty(self.shape) for _ in range(5)]
+        self._chk(self._L.oracle3d_get_fields(self.h, *[_ptr(a) for a in out]))
+        return out
+
+    def reduce(self):
+        out = np.empty(9)
+        self._chk(self._L.oracle3d_reduce(self.h, _ptr(out)))
+        return out
+
+    def node_forces(self, x, y, z):
+        out = np.empty(18)
+        self._chk(self._L.oracle3d_node_forces(self.h, x, y, z, _ptr(out)))
+        return out.reshape(6, 3)
+
+    def adhesion_vector(self, x, y, z):
+        out = np.empty(3)
+        self._chk(self._L.oracle3d_adhesion_vector(self.h, x, y, z, _ptr(out)))
+        return out
+
+    def interface_points(self, wall_kind, wall):
+        w = np.ascontiguousarray(wall, dtype=np.float64)
+        n = ctypes.c_int()
+        self._chk(self._L.oracle3d_interface_points(self.h, wall_kind, _ptr(w), None, None, None, 0,
+                                                    ctypes.byref(n)))
+        p = [np.empty(n.value) for _ in range(3)]
+        self._chk(self._L.oracle3d_interface_points(self.h, wall_kind, _ptr(w), *[_ptr(a) for a in p],
+                                                    n.value, ctypes.byref(n)))
+        return p
+
+    def contact_angle(self, wall_kind, wall):
+        w = np.ascontiguousarray(wall, dtype=np.float64)
+        th = ctypes.c_double()
+        self._chk(self._L.oracle3d_contact_angle(self.h, wall_kind, _ptr(w), ctypes.byref(th)))
+        return th.value
+
+
+def d3q19():
+    L = lib()
+    ex, ey, ez, opp = (np.empty(19, dtype=np.int32) for _ in range(4))
+    w = np.empty(19)
+    L.oracle3d_d3q19(_ptr(ex), _ptr(ey), _ptr(ez), _ptr(w), _ptr(opp))
+    return ex, ey, ez, w, opp
+
+
+def stencil3d():
+    L = lib()
+    ex, ey, ez, cp = (np.empty(92, dtype=np.int32) for _ in range(4))
+    W = np.empty(92)
+    n = L.oracle3d_stencil(_ptr(ex), _ptr(ey), _ptr(ez), _ptr(W), _ptr(cp))
+    return ex[:n], ey[:n], ez[:n], W[:n], cp[:n]
+
+
+def equilibrium3d(rho, u):
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty(19)
+    lib().oracle3d_equilibrium(float(rho), _ptr(uu), _ptr(out))
+    return out
+
+
+def forcing3d(F, u):
+    FF = np.ascontiguousarray(F, dtype=np.float64)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty(19)
+    lib().oracle3d_forcing(_ptr(FF), _ptr(uu), _ptr(out))
+    return out
+
+
+def sphere_fit(px, py, pz):
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (px, py, pz)]
+    out = np.empty(4)
+    rc = lib().oracle3d_sphere_fit(*[_ptr(v) for v in a], len(a[0]), _ptr(out))
+    if rc:
+        raise OracleError(rc, "sphere fit failed")
+    return out

@@ -357,3 +357,131 @@ def random_populations(seed: int, wl: Workload, amplitude: float = 0.2) -> np.nd
     f = base * (1.0 + amplitude * rng.uniform(-1.0, 1.0, size=(2, 9, wl.ny, wl.nx)))
     f[:, :, wl.solid != 0] = 0.0
     return f
+
+
+# ---------------------------------------------------------------------------
+# Three dimensions (Sec. 3.5): arrays are [nz, ny, nx], node id
+# (z * ny + y) * nx + x.
+# ---------------------------------------------------------------------------
+PERIODIC_Z = 2048
+WALL_SPHERE = 1
+
+
+@dataclasses.dataclass
+class Workload3D:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    flags: int
+    solid: np.ndarray            # uint8 [nz, ny, nx], 1 = solid
+    rho1: np.ndarray             # float64 [nz, ny, nx]
+    rho2: np.ndarray
+    G_c: float = 0.9
+    G_ads: float = 0.0
+    tau: float = 1.0
+    accel: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0)  # g1 (x, y, z), g2 (x, y, z)
+    steps: int = 1000
+    wall_kind: Optional[int] = None
+    wall: Optional[Tuple[float, float, float, float]] = None
+
+    @property
+    def n_nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_fluid(self) -> int:
+        return int(self.n_nodes - int(self.solid.sum()))
+
+
+def _grid3(nx: int, ny: int, nz: int):
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx]
+    return x.astype(np.float64), y.astype(np.float64), z.astype(np.float64)
+
+
+def g_ads_of_lambda(lam: float, G_c: float = 0.9) -> float:
+    """G_ads whose lambda = G_w1 / G_w2 = 1 + 2 G_ads / G_c is `lam`."""
+    return (lam - 1.0) * G_c / 2.0
+
+
+SPHERE_LAMBDAS = [0.38, 1.0, 2.1]
+
+
+def sphere_drop(lam: float = 1.0, nx: int = 200, ny: int = 200, nz: int = 280, R: float = 50.0,
+                centre=(100.0, 100.0, 100.0), r_drop: float = 45.0, drop_centre=(100.0, 100.0, 180.0),
+                G_c: float = 0.9, tau: float = 1.0, steps: int = 20000,
+                major: float = RHO_MAJOR_EQ, minor: float = RHO_MINOR_EQ) -> Workload3D:
+    """Droplet on a solid sphere in a fully periodic box (Sec. 3.5: 200 x 200
+    x 280, sphere R = 50 at (100, 100, 100), droplet r = 45 at (100, 100,
+    180), lambda = 0.38 / 1 / 2.1).  Solid where |x - c| < R (strict);
+    droplet strict too; the spheres overlap by 15 as set up in the paper.
+    Starts at the coexisting densities of G_c = 0.9; the wall surface for
+    the angle is R + 0.5."""
+    x, y, z = _grid3(nx, ny, nz)
+    solid = (((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2) < R * R).astype(np.uint8)
+    inside = (x - drop_centre[0]) ** 2 + (y - drop_centre[1]) ** 2 + (z - drop_centre[2]) ** 2 < r_drop * r_drop
+    rho1, rho2 = _two_phase(inside, solid, major, minor)
+    return Workload3D("sphere_drop", nx, ny, nz, PERIODIC_X | PERIODIC_Y | PERIODIC_Z, solid, rho1, rho2,
+                      G_c=G_c, G_ads=g_ads_of_lambda(lam, G_c), tau=tau, steps=steps, wall_kind=WALL_SPHERE,
+                      wall=(centre[0], centre[1], centre[2], R + 0.5))
+
+
+def flat_drop3d(nx: int = 40, ny: int = 40, nz: int = 24, radius: float = 10.0, G_ads: float = 0.0,
+                G_c: float = 0.9, tau: float = 1.0, steps: int = 2000, major: float = RHO_MAJOR_EQ,
+                minor: float = RHO_MINOR_EQ) -> Workload3D:
+    """Hemispherical cap on the wall z = 0: solid planes z = 0 and z = nz-1,
+    periodic in x and y, droplet |x - (nx/2, ny/2, 0.5)| < r (strict); the
+    wall plane for the angle is z = 0.5."""
+    x, y, z = _grid3(nx, ny, nz)
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    solid[0] = 1
+    solid[nz - 1] = 1
+    inside = (x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2 + (z - 0.5) ** 2 < radius * radius
+    rho1, rho2 = _two_phase(inside, solid, major, minor)
+    return Workload3D("flat_drop3d", nx, ny, nz, PERIODIC_X | PERIODIC_Y, solid, rho1, rho2, G_c=G_c,
+                      G_ads=G_ads, tau=tau, steps=steps, wall_kind=WALL_FLAT, wall=(0.5, 0.0, 0.0, 0.0))
+
+
+def random_small3d(seed: int, nx: int = 14, ny: int = 12, nz: int = 10,
+                   flags: int = PERIODIC_X | PERIODIC_Y | PERIODIC_Z, n_blobs: int = 3,
+                   speckle: float = 0.0) -> Workload3D:
+    """Small random 3-D geometry for parity cases: balls and boxes at least
+    2 nodes thick (or, with `speckle` > 0, that fraction of single solid
+    voxels), a random droplet, and a seeded perturbation of the densities."""
+    rng = np.random.default_rng(seed)
+    x, y, z = _grid3(nx, ny, nz)
+    solid = np.zeros((nz, ny, nx), dtype=np.uint8)
+    if speckle > 0.0:
+        solid |= (rng.random((nz, ny, nx)) < speckle).astype(np.uint8)
+    else:
+        for _ in range(n_blobs):
+            c = (rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz))
+            r = rng.uniform(1.5, 3.0)
+            d = []
+            for v, cc, n, bit in ((x, c[0], nx, PERIODIC_X), (y, c[1], ny, PERIODIC_Y), (z, c[2], nz, PERIODIC_Z)):
+                dv = np.abs(v - cc)
+                d.append(np.minimum(dv, n - dv) if flags & bit else dv)
+            if int(rng.integers(0, 2)) == 0:
+                solid |= ((d[0] ** 2 + d[1] ** 2 + d[2] ** 2) <= r * r).astype(np.uint8)
+            else:
+                solid |= ((d[0] <= r) & (d[1] <= r) & (d[2] <= r)).astype(np.uint8)
+    dc = (rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz))
+    dr = rng.uniform(2.5, min(nx, ny, nz) / 3.0)
+    inside = (x - dc[0]) ** 2 + (y - dc[1]) ** 2 + (z - dc[2]) ** 2 < dr * dr
+    rho1, rho2 = _two_phase(inside, solid)
+    pert = rng.uniform(-0.01, 0.01, size=(2, nz, ny, nx))
+    rho1 = np.where(solid != 0, 0.0, rho1 + pert[0] * rho1)
+    rho2 = np.where(solid != 0, 0.0, rho2 + pert[1] * rho2)
+    acc = tuple(float(v) for v in rng.uniform(-1e-4, 1e-4, size=6))
+    return Workload3D("random_small3d", nx, ny, nz, flags, solid, rho1, rho2, G_c=0.9,
+                      G_ads=float(rng.uniform(-0.3, 0.3)), tau=float(rng.uniform(0.7, 1.3)), accel=acc, steps=100)
+
+
+def random_populations3d(seed: int, wl: Workload3D, amplitude: float = 0.2) -> np.ndarray:
+    """Seeded non-equilibrium population set [2, 19, nz, ny, nx]:
+    f_i = rho_k / 19 * (1 + a U[-1, 1)), zero on solid nodes."""
+    rng = np.random.default_rng(seed)
+    base = np.stack([wl.rho1, wl.rho2])[:, None] / 19.0
+    f = base * (1.0 + amplitude * rng.uniform(-1.0, 1.0, size=(2, 19, wl.nz, wl.ny, wl.nx)))
+    f[:, :, wl.solid != 0] = 0.0
+    return f
