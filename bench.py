@@ -478,6 +478,68 @@ def obstacle_flow(args):
                                   f"{steps} steps", "rows": rows}), flush=True)
 
 
+def sphere_drop(args):
+    """The 3-D case of Sec. 3.5: a droplet (r = 45) on a sphere (R = 50) in
+    a periodic 200 x 200 x 280 box, D3Q19 with the 92-position stencil.
+    Times `--steps` steps (5 repeats, median) at lambda = 0.38 in the chosen
+    storage and reports MLUPS and the HBM roofline fraction (algorithmic
+    bytes 2 x 19 x (read + write) x element + 1 per fluid update); with
+    --full, runs 20000 steps at each lambda of the paper (0.38, 1, 2.1) and
+    reports the contact angles."""
+    import torch
+    storage = STORAGES[args.storage]
+    steps = args.steps if args.steps_given else 500
+    flags = lbm.ROUND_NEAREST if args.nearest else 0
+    wl = W.sphere_drop(lam=0.38)
+    stream = torch.cuda.Stream()
+    g = lbm.lattice3d_from_workload(wl, storage, flags)
+    g.set_stream(stream.cuda_stream)
+    if args.tile not in ("default", "auto"):
+        vals = [int(v) for v in args.tile.split(",")]
+        g.set_tile(vals[0], vals[1], vals[2])
+    reps = 5
+    chunk = [max(1, steps // reps)] * reps
+    with torch.cuda.stream(stream):
+        g.step(args.warmup)
+        g.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        evs[0].record(stream)
+        for r in range(reps):
+            g.step(chunk[r])
+            evs[r + 1].record(stream)
+        evs[-1].synchronize()
+    rep = [evs[r].elapsed_time(evs[r + 1]) / chunk[r] for r in range(reps)]
+    ms_step = float(np.median(rep))
+    n_fluid, bpu = g.fluid_nodes, g.bytes_per_update
+    achieved = bpu * n_fluid / (ms_step * 1e-3) / 1e9
+    m = g.reduce()
+    out = {"metric": "3-D two-component D3Q19 MLUPS and contact angle on a sphere",
+           "workload": f"sphere 200x200x280 (R = 50, droplet r = 45, overlap 15), lambda = 0.38, {args.storage} storage"
+                       + rounding_label(args),
+           "value": round(n_fluid / (ms_step * 1e-3) / 1e6, 1), "unit": "MLUPS", "fluid_nodes": n_fluid,
+           "ms_per_step": round(ms_step, 5), "repeats_ms_per_step": [round(v, 5) for v in rep],
+           "tile": list(g.get_tile()),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_update": bpu},
+           "mass1": float(m[0]), "mass2": float(m[1]), "max_u": float(m[5]), "nonfinite": int(m[8])}
+    g.close()
+    if args.full:
+        th = {}
+        for lam in W.SPHERE_LAMBDAS:
+            wl = W.sphere_drop(lam=lam)
+            g = lbm.lattice3d_from_workload(wl, storage, flags)
+            g.step(wl.steps)
+            try:
+                th[str(lam)] = round(g.contact_angle(wl.wall_kind, wl.wall), 3)
+            except lbm.LbmError as e:
+                th[str(lam)] = str(e)
+            g.close()
+            print(f"[sphere] lambda {lam}: theta {th[str(lam)]}", file=sys.stderr, flush=True)
+        out["theta_deg"] = th
+        out["steps_full"] = W.sphere_drop().steps
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,12 +556,13 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--workload", default="constrictions",
                     choices=["constrictions", "calibration", "porous", "cylinder", "schemes", "open",
-                             "cocurrent", "obstacle"],
+                             "cocurrent", "obstacle", "sphere"],
                     help="constrictions: the 16384x2048 channel (default); calibration: the 512-run batch; "
                          "porous: the storage precision study; cylinder: the contact-angle sweep per storage; "
                          "schemes: original against improved adhesion; open: the channel with an inlet and "
                          "an outflow against the periodic one; cocurrent: Couette and Poiseuille layers; "
-                         "obstacle: a droplet past a square, original against improved adhesion")
+                         "obstacle: a droplet past a square, original against improved adhesion; sphere: the "
+                         "3-D droplet on a sphere (200x200x280)")
     ap.add_argument("--record-every", type=int, default=1000, help="porous: recording interval")
     ap.add_argument("--full", action="store_true", help="calibration: run the configured 10000 steps and "
                     "report contact angles")
@@ -545,6 +608,9 @@ def main():
         return
     if args.workload == "obstacle":
         obstacle_flow(args)
+        return
+    if args.workload == "sphere":
+        sphere_drop(args)
         return
 
     import torch  # device streams and events only

@@ -107,7 +107,7 @@ enum {
 };
 
 /* Tile schedule bits for lbm_set_tile. */
-enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2, LBM_SCHED_XCD_SLABS = 4, LBM_SCHED_TWO_STEP = 8 };
+enum { LBM_SCHED_ALIGN = 1, LBM_SCHED_BANDS = 2, LBM_SCHED_XCD_SLABS = 4, LBM_SCHED_TWO_STEP = 8, LBM_SCHED_REPULL = 16 };
 
 /* Contact-angle wall kinds for lbm_contact_angle. */
 enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
@@ -298,7 +298,12 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * current tile and then every candidate for `steps` steps each on the
  * current state (restoring state and time afterwards); a candidate replaces
  * the best so far only when it is at least 2 % faster, so timing noise does
- * not move the choice between near-equal tiles. */
+ * not move the choice between near-equal tiles.  LBM_SCHED_REPULL (with
+ * LBM_SCHED_TWO_STEP, 64- or 128-thread strips, closed lattices without
+ * sliding walls) makes the first of the two fused steps pull each row
+ * again when it finishes it instead of holding the pulled rows in
+ * registers: fewer registers per thread, one more read of each row
+ * through the caches; results are unchanged (bitwise). */
 int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched);
 int lbm_get_tile(const lbm_ctx *c, int *block, int *seg_rows, unsigned *sched);
 int lbm_autotune(lbm_ctx *c, int steps);

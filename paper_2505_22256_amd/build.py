@@ -13,16 +13,22 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = [os.path.join(CSRC, n) for n in ("lbm_api.hip", "lbm_batch.hip", "lbm_launch_f64.hip", "lbm_launch_f32.hip",
-                                         "lbm_launch_f16.hip", "lbm_launch_bf16.hip")]
+# the longest units first, so that the parallel build ends soonest
+SOURCES = [os.path.join(CSRC, n) for n in ("lbm_launch_f32.hip", "lbm_launch_f16.hip", "lbm_launch_bf16.hip",
+                                         "lbm_launch_f64.hip", "lbm_batch.hip", "lbm_api.hip",
+                                         "lbm3d_launch_f64.hip", "lbm3d_launch_f32.hip", "lbm3d_launch_f16.hip",
+                                         "lbm3d_launch_bf16.hip", "lbm3d_api.hip")]
 HEADERS = [os.path.join(CSRC, n) for n in ("lbm_device.hpp", "lbm_kernels.hpp", "lbm_params.hpp", "lbm_contact.hpp",
-                                            "lbm_launch.hpp", "lbm_launch_impl.hpp")] + [os.path.join(ROOT, "include", "lbm.h")]
+                                            "lbm_launch.hpp", "lbm_launch_impl.hpp", "lbm3d_kernels.hpp",
+                                            "lbm3d_contact.hpp", "lbm3d_launch.hpp", "lbm3d_launch_impl.hpp")] + \
+    [os.path.join(ROOT, "include", "lbm.h"), os.path.join(ROOT, "include", "lbm3d.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
@@ -51,9 +57,17 @@ def build(force: bool = True, verbose: bool = False) -> str:
                 if verbose:
                     print(" ".join(cmd), flush=True)
                 procs.append((subprocess.Popen(cmd), src))
-            proc, src = procs.pop(0)
-            if proc.wait() != 0:
-                raise subprocess.CalledProcessError(proc.returncode, src)
+            # wait for whichever compile ends first, so a free slot is
+            # refilled at once
+            while True:
+                done = [(p, sname) for p, sname in procs if p.poll() is not None]
+                if done:
+                    break
+                time.sleep(0.2)
+            for proc, src in done:
+                procs.remove((proc, src))
+                if proc.returncode != 0:
+                    raise subprocess.CalledProcessError(proc.returncode, src)
         tmp = LIB + ".tmp" + tag
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
         if verbose:

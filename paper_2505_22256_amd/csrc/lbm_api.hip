@@ -161,7 +161,8 @@ int resident_capacity(lbm_ctx *c, int block)
 // Launch one pass reading buf[cur].  P_STEP* write buf[cur^1] (the caller
 // flips cur).  Returns the number of partial records in *nparts.
 template <int S>
-int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts)
+int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts,
+               double *partials = nullptr, int max_parts = 0)
 {
     using C = typename Traits<S>::C;
     const bool two = pass == P_STEP2 || pass == P_STEP2_RED1 || pass == P_STEP2_RED2;
@@ -184,7 +185,14 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
     }
     const int grid = ((p.n_units + 7) / 8) * 8;
     if (nparts) *nparts = grid;
-    if (pass == P_STEP_REDUCE || pass == P_FIELDS_REDUCE || pass == P_STEP2_RED1 || pass == P_STEP2_RED2) {
+    if (partials) {
+        // a caller-provided partials area (no allocation)
+        if (grid > max_parts)
+            return set_err(c, LBM_EINVAL, "%d workgroup partials exceed the %d the scratch array holds", grid,
+                           max_parts);
+        p.partials = partials;
+    } else if (pass == P_STEP_REDUCE || pass == P_FIELDS_REDUCE || pass == P_STEP2_RED1 || pass == P_STEP2_RED2 ||
+               pass == P_REDUCE) {
         int rc = ensure_partials(c, (size_t)grid);
         if (rc) return rc;
         p.partials = c->d_partials;
@@ -200,18 +208,19 @@ int run_pass_t(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw
     p.tab_src = src;
     if (pass == P_TABLES) p.plain = 1;  // link bits: plain unavailability of each source
     const bool sr = (S == ST_F16 || S == ST_BF16) && (c->flags & LBM_ROUND_STOCHASTIC);
-    const hipError_t e = launch_pass<S>(p, pass, block, sr, boundary_steps(c), c->stream);
+    const hipError_t e = launch_pass<S>(p, pass, block, sr, boundary_steps(c), c->stream, (c->sched & SCHED_REPULL) != 0);
     if (e != hipSuccess) return set_err(c, LBM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
 
-int run_pass(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts)
+int run_pass(lbm_ctx *c, Pass pass, double *fields, uint8_t *link, uint8_t *nw, int32_t *src, int *nparts,
+             double *partials = nullptr, int max_parts = 0)
 {
     switch (c->storage) {
-    case LBM_F64: return run_pass_t<ST_F64>(c, pass, fields, link, nw, src, nparts);
-    case LBM_F32: return run_pass_t<ST_F32>(c, pass, fields, link, nw, src, nparts);
-    case LBM_F16: return run_pass_t<ST_F16>(c, pass, fields, link, nw, src, nparts);
-    default: return run_pass_t<ST_BF16>(c, pass, fields, link, nw, src, nparts);
+    case LBM_F64: return run_pass_t<ST_F64>(c, pass, fields, link, nw, src, nparts, partials, max_parts);
+    case LBM_F32: return run_pass_t<ST_F32>(c, pass, fields, link, nw, src, nparts, partials, max_parts);
+    case LBM_F16: return run_pass_t<ST_F16>(c, pass, fields, link, nw, src, nparts, partials, max_parts);
+    default: return run_pass_t<ST_BF16>(c, pass, fields, link, nw, src, nparts, partials, max_parts);
     }
 }
 
@@ -820,8 +829,10 @@ int lbm_get_tables(lbm_ctx *c, uint8_t *link, int32_t *nw_list, int32_t *nw_src,
 int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
 {
     if (!c) return LBM_EINVAL;
-    if (!valid_block(block) || seg_rows < 0 || (sched & ~15u))
-        return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..15");
+    if (!valid_block(block) || seg_rows < 0 || (sched & ~31u))
+        return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..31");
+    if ((sched & SCHED_REPULL) && !(sched & SCHED_TWO_STEP))
+        return set_err(c, LBM_EINVAL, "LBM_SCHED_REPULL needs LBM_SCHED_TWO_STEP");
     if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64)
         return set_err(c, LBM_EINVAL, "two fused steps need FP32, FP16 or BF16 storage");
     c->block = block;

@@ -42,7 +42,8 @@ enum : int {
     M_LDS = 32,    // first of two fused steps: post-collision values to the LDS ring
     M_TWO = 64,    // kernel advances two steps per launch
     M_DIAG_FIRST = 128,  // two steps: M_REDUCE records the first step (else the second)
-    M_BND = 256          // open and moving boundaries compiled in (else plain walls only)
+    M_BND = 256,         // open and moving boundaries compiled in (else plain walls only)
+    M_REPULL = 512       // two steps: the first step pulls a row again when it finishes it
 };
 
 // ---------------------------------------------------------------------------

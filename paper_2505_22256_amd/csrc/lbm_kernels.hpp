@@ -887,6 +887,11 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     constexpr bool red2 = (MODE & M_REDUCE) && !(MODE & M_DIAG_FIRST);
     constexpr int M1 = (MODE & (M_SR | M_BND)) | M_STORE | M_LDS | (red1 ? M_REDUCE : 0);
     constexpr int M2 = (MODE & (M_SR | M_BND)) | M_STORE | (red2 ? M_REDUCE : 0);
+    // with M_REPULL the first step keeps no pulled rows in registers: it
+    // pulls the row it finishes again (the second read of addresses read
+    // two iterations earlier, served by the caches), which frees the
+    // registers of two row states
+    constexpr bool REPULL = (MODE & M_REPULL) != 0;
     const int tid = threadIdx.x;
     int x0, x1;
     if (p.strip_w > 0) {
@@ -912,15 +917,26 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     RawRow<S> q;
     issue_row<S>(p, mr, cx, act1, p_first, q);
     auto iter = [&](int pp, RowState<C> &s1w, RowState<C> &s1f, RowState<C> &s2w, RowState<C> &s2f) {
+        const bool fin1 = in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2;
+        RawRow<S> qf;
+        if constexpr (REPULL) {
+            if (fin1) issue_row<S>(p, mr, cx, act1, pp - 2, qf);
+        }
         if (pp <= p_pull_last) process_row<S, BLOCK, TWO_PR, BND>(p, mr, cx, act1, pp, q, ring1, s1w);
         if (pp + 1 <= p_pull_last) issue_row<S>(p, mr, cx, act1, pp + 1, q);
         __syncthreads();
-        const bool fin1 = in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2;
         FPending<S> pend;
         if (fin1) {
             const Axis ry = make_axis_near(pp - 2, p.ny, wrap_y);
             const bool core = core_col && pp - 2 >= y0 && pp - 2 < y1;
-            finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, s1f, ring1, acc, fring, 0u, &pend, core);
+            if constexpr (REPULL) {
+                RowState<C> st;
+                C r1 = 0, r2 = 0;
+                process_node<S, BND>(p, mr, cx, ry, act1 && ry.ok, qf, st, r1, r2);
+                finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, st, ring1, acc, fring, 0u, &pend, core);
+            } else {
+                finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, s1f, ring1, acc, fring, 0u, &pend, core);
+            }
         }
         __syncthreads();
         if (pp - 3 >= y0 - 2 && pp - 3 <= y1 + 1) process_row_lds<S, BLOCK, BND>(p, fring, cx, act2, pp - 3, ring2, s2w);

@@ -2,6 +2,6 @@
 #include "lbm_launch_impl.hpp"
 
 namespace lbm_host {
-template hipError_t launch_pass<lbm::ST_BF16>(const lbm::KParams<float> &, Pass, int, bool, bool, hipStream_t);
+template hipError_t launch_pass<lbm::ST_BF16>(const lbm::KParams<float> &, Pass, int, bool, bool, hipStream_t, bool);
 template int step_occupancy<lbm::ST_BF16>(int);
 }  // namespace lbm_host

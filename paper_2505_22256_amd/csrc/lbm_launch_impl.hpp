@@ -47,10 +47,19 @@ hipError_t launch_step2_b(const KParams<typename Traits<S>::C> &p, int block, hi
 }
 
 template <int S, int B>
-hipError_t launch_pass_b(const KParams<typename Traits<S>::C> &p, Pass pass, int block, bool sr, hipStream_t st)
+hipError_t launch_pass_b(const KParams<typename Traits<S>::C> &p, Pass pass, int block, bool sr, hipStream_t st,
+                         bool repull)
 {
     constexpr bool narrow = S == ST_F16 || S == ST_BF16;
     constexpr int R1 = M_REDUCE | M_DIAG_FIRST, R2 = M_REDUCE;
+    if constexpr (S != ST_F64 && B == 0) {
+        // the re-pull variant of the plain two-step pass (the 1-in-K
+        // diagnostic passes keep the other: the results are the same)
+        if (repull && pass == P_STEP2 && block != 256) {
+            if (narrow && sr) return launch_step2_b<S, M_STORE | M_SR | M_REPULL>(p, block, st);
+            return launch_step2_b<S, M_STORE | M_REPULL>(p, block, st);
+        }
+    }
     if constexpr (narrow) {
         if (sr) {
             switch (pass) {
@@ -67,7 +76,8 @@ hipError_t launch_pass_b(const KParams<typename Traits<S>::C> &p, Pass pass, int
     case P_STEP: return launch_step_b<S, B | M_STORE>(p, block, st);
     case P_STEP_REDUCE: return launch_step_b<S, B | M_STORE | M_REDUCE>(p, block, st);
     case P_FIELDS_REDUCE:
-    case P_TABLES: return hipErrorInvalidValue;  // launched by launch_pass
+    case P_TABLES:
+    case P_REDUCE: return hipErrorInvalidValue;  // launched by launch_pass
     case P_STEP2:
     case P_STEP2_RED1:
     case P_STEP2_RED2:
@@ -85,11 +95,14 @@ hipError_t launch_pass_b(const KParams<typename Traits<S>::C> &p, Pass pass, int
 // Stepping passes take the instance without boundary code unless open or
 // moving boundaries are on; the (rare) field and table passes always have it.
 template <int S>
-hipError_t launch_pass(const KParams<typename Traits<S>::C> &p, Pass pass, int block, bool sr, bool bnd, hipStream_t st)
+hipError_t launch_pass(const KParams<typename Traits<S>::C> &p, Pass pass, int block, bool sr, bool bnd, hipStream_t st,
+                       bool repull)
 {
     if (pass == P_FIELDS_REDUCE) return launch_step_t<S, 256, M_BND | M_FIELDS | M_REDUCE>(p, st);
+    if (pass == P_REDUCE) return launch_step_t<S, 256, M_BND | M_REDUCE>(p, st);
     if (pass == P_TABLES) return launch_step_t<S, 256, M_BND | M_TABLES>(p, st);
-    return bnd ? launch_pass_b<S, M_BND>(p, pass, block, sr, st) : launch_pass_b<S, 0>(p, pass, block, sr, st);
+    return bnd ? launch_pass_b<S, M_BND>(p, pass, block, sr, st, false)
+               : launch_pass_b<S, 0>(p, pass, block, sr, st, repull);
 }
 
 template <int S, int BLOCK>

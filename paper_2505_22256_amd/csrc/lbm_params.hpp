@@ -12,7 +12,7 @@ using lbm::KParams;
 using lbm::qw;
 
 // Schedule bits of a tile (lbm_set_tile).
-enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u, SCHED_XCD_SLABS = 4u, SCHED_TWO_STEP = 8u };
+enum : unsigned { SCHED_ALIGN = 1u, SCHED_BANDS = 2u, SCHED_XCD_SLABS = 4u, SCHED_TWO_STEP = 8u, SCHED_REPULL = 16u };
 
 // Rounding of the stores in effect for a storage type: F16 and BF16 round
 // stochastically unless LBM_ROUND_NEAREST asks for round-to-nearest-even;

@@ -35,7 +35,9 @@ ROUND_STOCHASTIC = 128
 INLET, OUTFLOW = 256, 512
 ROUND_NEAREST = 1024
 WALL_FLAT, WALL_CYLINDER = 0, 1
-SCHED_ALIGN, SCHED_BANDS, SCHED_XCD_SLABS, SCHED_TWO_STEP = 1, 2, 4, 8
+L3_PERIODIC_Z = 2048
+L3_WALL_FLAT, L3_WALL_SPHERE = 0, 1
+SCHED_ALIGN, SCHED_BANDS, SCHED_XCD_SLABS, SCHED_TWO_STEP, SCHED_REPULL = 1, 2, 4, 8, 16
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 
 _P = ctypes.c_void_p
@@ -101,6 +103,29 @@ SIGNATURES = {
     "lbm_batch_fluid_nodes": (_L, [_P]),
     "lbm_batch_last_error": (ctypes.c_char_p, [_P]),
     "lbm_batch_destroy": (None, [_P]),
+    # three dimensions (include/lbm3d.h)
+    "lbm3d_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _I, _U]),
+    "lbm3d_get_flags": (_U, [_P]),
+    "lbm3d_set_geometry": (_I, [_P, _P]),
+    "lbm3d_set_params": (_I, [_P, _D, _D, _D]),
+    "lbm3d_set_adhesion": (_I, [_P, _D, _D, _D]),
+    "lbm3d_set_body_accel": (_I, [_P, _P]),
+    "lbm3d_init_fields": (_I, [_P, _P, _P]),
+    "lbm3d_set_populations": (_I, [_P, _P]),
+    "lbm3d_get_populations": (_I, [_P, _P]),
+    "lbm3d_step": (_I, [_P, _I]),
+    "lbm3d_synchronize": (_I, [_P]),
+    "lbm3d_time": (_L, [_P]),
+    "lbm3d_get_fields": (_I, [_P, _P, _P, _P, _P, _P]),
+    "lbm3d_reduce": (_I, [_P, _P]),
+    "lbm3d_contact_angle": (_I, [_P, _I, _P, ctypes.POINTER(_D)]),
+    "lbm3d_set_tile": (_I, [_P, _I, _I, _I]),
+    "lbm3d_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "lbm3d_set_stream": (_I, [_P, _P]),
+    "lbm3d_fluid_nodes": (_L, [_P]),
+    "lbm3d_bytes_per_update": (_I, [_P]),
+    "lbm3d_last_error": (ctypes.c_char_p, [_P]),
+    "lbm3d_destroy": (None, [_P]),
 }
 
 _lib = None
@@ -452,3 +477,120 @@ class Batch:
     @property
     def fluid_nodes(self):
         return self._L.lbm_batch_fluid_nodes(self.h)
+
+
+class Lattice3D:
+    """One 3-D context (include/lbm3d.h): arrays are [nz, ny, nx],
+    populations [2, 19, nz, ny, nx]."""
+
+    def __init__(self, nx: int, ny: int, nz: int, storage: int = F32, flags: int = 0):
+        self._L = load_library()
+        h = _P()
+        rc = self._L.lbm3d_create(ctypes.byref(h), nx, ny, nz, storage, flags)
+        if rc:
+            raise LbmError(rc, "lbm3d_create failed")
+        self.h = h
+        self.nx, self.ny, self.nz, self.storage, self.flags = nx, ny, nz, storage, flags
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.lbm3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def _c(self, rc):
+        if rc:
+            raise LbmError(rc, self._L.lbm3d_last_error(self.h).decode())
+        return rc
+
+    def flags_in_effect(self) -> int:
+        return int(self._L.lbm3d_get_flags(self.h))
+
+    def set_geometry(self, solid):
+        a = np.ascontiguousarray(solid, dtype=np.uint8).reshape(self.shape)
+        self._c(self._L.lbm3d_set_geometry(self.h, _ptr(a)))
+
+    def set_params(self, G_c, G_ads, tau):
+        self._c(self._L.lbm3d_set_params(self.h, G_c, G_ads, tau))
+
+    def set_adhesion(self, G_w1, G_w2, delta=0.8):
+        self._c(self._L.lbm3d_set_adhesion(self.h, G_w1, G_w2, delta))
+
+    def set_body_accel(self, g):
+        a = np.ascontiguousarray(g, dtype=np.float64).reshape(6)
+        self._c(self._L.lbm3d_set_body_accel(self.h, _ptr(a)))
+
+    def init_fields(self, rho1, rho2):
+        a = np.ascontiguousarray(rho1, dtype=np.float64).reshape(self.shape)
+        b = np.ascontiguousarray(rho2, dtype=np.float64).reshape(self.shape)
+        self._c(self._L.lbm3d_init_fields(self.h, _ptr(a), _ptr(b)))
+
+    def set_populations(self, f):
+        a = np.ascontiguousarray(f, dtype=np.float64).reshape((2, 19) + self.shape)
+        self._c(self._L.lbm3d_set_populations(self.h, _ptr(a)))
+
+    def get_populations(self):
+        a = np.empty((2, 19) + self.shape)
+        self._c(self._L.lbm3d_get_populations(self.h, _ptr(a)))
+        return a
+
+    def step(self, n=1):
+        self._c(self._L.lbm3d_step(self.h, int(n)))
+
+    def synchronize(self):
+        self._c(self._L.lbm3d_synchronize(self.h))
+
+    @property
+    def time(self):
+        return self._L.lbm3d_time(self.h)
+
+    def get_fields(self):
+        out = [np.empty(self.shape) for _ in range(5)]
+        self._c(self._L.lbm3d_get_fields(self.h, *[_ptr(a) for a in out]))
+        return out
+
+    def reduce(self):
+        out = np.empty(9)
+        self._c(self._L.lbm3d_reduce(self.h, _ptr(out)))
+        return out
+
+    def contact_angle(self, wall_kind, wall):
+        w = np.ascontiguousarray(wall, dtype=np.float64).reshape(4)
+        th = _D()
+        self._c(self._L.lbm3d_contact_angle(self.h, wall_kind, _ptr(w), ctypes.byref(th)))
+        return th.value
+
+    def set_tile(self, bx, by, seg_planes):
+        self._c(self._L.lbm3d_set_tile(self.h, bx, by, seg_planes))
+
+    def get_tile(self):
+        a, b, c = _I(), _I(), _I()
+        self._c(self._L.lbm3d_get_tile(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_stream(self, stream_handle: Optional[int]):
+        self._c(self._L.lbm3d_set_stream(self.h, None if stream_handle is None else _P(stream_handle)))
+
+    @property
+    def fluid_nodes(self):
+        return self._L.lbm3d_fluid_nodes(self.h)
+
+    @property
+    def bytes_per_update(self):
+        return self._L.lbm3d_bytes_per_update(self.h)
+
+
+def lattice3d_from_workload(wl, storage: int = F32, flags_extra: int = 0) -> Lattice3D:
+    """3-D context initialised from a ``workloads.Workload3D``."""
+    lat = Lattice3D(wl.nx, wl.ny, wl.nz, storage, wl.flags | flags_extra)
+    lat.set_geometry(wl.solid)
+    lat.set_params(wl.G_c, wl.G_ads, wl.tau)
+    lat.set_body_accel(wl.accel)
+    lat.init_fields(wl.rho1, wl.rho2)
+    return lat

@@ -1,0 +1,194 @@
+"""GPU parity of the 3-D path (include/lbm3d.h) against the FP64 3-D oracle
+(Sec. 3.5).
+
+Tolerances as in 2-D: FP64 storage and arithmetic 1e-12 relative on the
+populations after up to 1000 steps (rounding order only); FP32 density
+within 1e-4 of the field maximum; FP16 / BF16 (stochastic rounding, the
+default) contact angle within 1 degree; tilings bitwise equal.  The
+sphere of Sec. 3.5 at its full 200 x 200 x 280 size is checked on
+sampled nodes, each advanced by the oracle on its 7 x 7 x 7 window, in the
+configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+from paper_2505_22256_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL64 = 1e-12
+P3 = W.PERIODIC_X | W.PERIODIC_Y | W.PERIODIC_Z
+
+
+def _relmax(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _pair(oracle_mod, lbm_mod, wl, storage, extra=0, pops=None, tile=None):
+    o = oracle_mod.Oracle3D(wl.nx, wl.ny, wl.nz, (wl.flags | extra) & ~(lbm_mod.ROUND_STOCHASTIC | lbm_mod.ROUND_NEAREST))
+    g = lbm_mod.Lattice3D(wl.nx, wl.ny, wl.nz, storage, wl.flags | extra)
+    for s in (o, g):
+        s.set_geometry(wl.solid)
+        s.set_params(wl.G_c, wl.G_ads, wl.tau)
+        s.set_body_accel(wl.accel)
+        if pops is None:
+            s.init_fields(wl.rho1, wl.rho2)
+        else:
+            s.set_populations(pops)
+    if tile is not None:
+        g.set_tile(*tile)
+    return o, g
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("extra", [0, 4, 8, 16, 32, 64])
+def test_fp64_random_geometry_random_populations(oracle_mod, lbm_mod, seed, extra):
+    """Random balls and boxes, a droplet, a non-equilibrium start, every
+    reading flag; periodic, partly periodic and closed boxes."""
+    flags = [P3, W.PERIODIC_X | W.PERIODIC_Z, 0][seed]
+    wl = W.random_small3d(100 + seed, nx=14 + seed, ny=11 + 2 * seed, nz=9 + seed, flags=flags)
+    f0 = W.random_populations3d(200 + seed, wl)
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, extra, f0, (32, 8, 4 + seed))
+    o.step(60)
+    g.step(60)
+    assert g.time == 60
+    assert _relmax(g.get_populations(), o.get_populations()) < REL64
+
+
+@pytest.mark.parametrize("extra", [0, 8, 16])
+def test_fp64_one_voxel_solids(oracle_mod, lbm_mod, extra):
+    """A fifth of the nodes single solid voxels: second-layer positions
+    behind one-node walls everywhere (the sign-rule copy)."""
+    wl = W.random_small3d(130, nx=13, ny=12, nz=11, speckle=0.2)
+    f0 = W.random_populations3d(131, wl, amplitude=0.1)
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, extra, f0, (32, 16, 5))
+    o.step(40)
+    g.step(40)
+    ref = o.get_populations()
+    assert np.all(np.isfinite(ref))
+    assert _relmax(g.get_populations(), ref) < REL64
+
+
+def test_fp64_flat_cap_1000_steps(oracle_mod, lbm_mod):
+    """Cap on a flat wall, walls top and bottom, 1000 steps, FP64: the
+    populations, the fields and the contact angle."""
+    wl = W.flat_drop3d(nx=24, ny=22, nz=14, radius=7.0, G_ads=W.g_ads_of_lambda(1.1))
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, tile=(64, 8, 7))
+    o.step(1000)
+    g.step(1000)
+    assert _relmax(g.get_populations(), o.get_populations()) < REL64
+    for a, b in zip(g.get_fields(), o.get_fields()):
+        assert np.max(np.abs(a - b)) < REL64 * max(np.max(np.abs(b)), 1e-3)
+    to, tg = o.contact_angle(0, wl.wall), g.contact_angle(0, wl.wall)
+    assert abs(to - tg) < 1e-8, (to, tg)
+
+
+def test_multitile_ragged(oracle_mod, lbm_mod):
+    """Several tiles and z segments with ragged edges, closed x, y and z."""
+    wl = W.random_small3d(140, nx=67, ny=29, nz=23, flags=0, n_blobs=6)
+    f0 = W.random_populations3d(141, wl)
+    ref = None
+    for tile in ((32, 8, 6), (64, 8, 23), (32, 16, 1)):
+        o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, pops=f0, tile=tile)
+        if ref is None:
+            o.step(25)
+            ref = o.get_populations()
+        g.step(25)
+        assert _relmax(g.get_populations(), ref) < REL64, tile
+
+
+def test_tiling_does_not_change_results(lbm_mod):
+    wl = W.random_small3d(150, nx=40, ny=33, nz=26, n_blobs=5)
+    ref = None
+    for tile in ((32, 8, 32), (32, 16, 5), (64, 8, 9), (32, 8, 1)):
+        g = lbm_mod.lattice3d_from_workload(wl, lbm_mod.F32)
+        g.set_tile(*tile)
+        g.step(30)
+        f = g.get_populations()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), tile
+
+
+def test_reduce_matches_oracle(oracle_mod, lbm_mod):
+    wl = W.random_small3d(160, nx=16, ny=15, nz=14)
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64)
+    o.step(30)
+    g.step(30)
+    a, b = g.reduce(), o.reduce()
+    assert np.all(np.abs(a - b) <= 1e-12 * np.maximum(np.abs(b), 1e-300) + 1e-15), (a, b)
+
+
+def test_fp32_density(oracle_mod, lbm_mod):
+    wl = W.flat_drop3d(nx=24, ny=24, nz=14, radius=7.0, G_ads=W.g_ads_of_lambda(1.4))
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F32)
+    o.step(400)
+    g.step(400)
+    ro, go = o.get_fields(), g.get_fields()
+    for k in (0, 1):
+        assert np.max(np.abs(go[k] - ro[k])) <= 1e-4 * np.max(np.abs(ro[k]))
+
+
+@pytest.mark.parametrize("lam", [0.6, 1.3])
+@pytest.mark.parametrize("storage,tol", [(1, 0.5), (2, 1.0), (3, 1.0)])
+def test_reduced_storage_contact_angle(oracle_mod, lbm_mod, storage, tol, lam):
+    """Flat-wall caps after 1500 steps (about 48 and 123 degrees), contact
+    angle against the oracle."""
+    wl = W.flat_drop3d(nx=28, ny=28, nz=16, radius=8.0, G_ads=W.g_ads_of_lambda(lam))
+    o, g = _pair(oracle_mod, lbm_mod, wl, storage)
+    o.step(1500)
+    g.step(1500)
+    to, tg = o.contact_angle(0, wl.wall), g.contact_angle(0, wl.wall)
+    assert abs(to - tg) < tol, (to, tg)
+
+
+def test_refusals(lbm_mod):
+    with pytest.raises(lbm_mod.LbmError):
+        lbm_mod.Lattice3D(4, 9, 9)
+    with pytest.raises(lbm_mod.LbmError):
+        lbm_mod.Lattice3D(9, 9, 9, lbm_mod.F32, lbm_mod.INLET)
+    g = lbm_mod.Lattice3D(9, 9, 9, lbm_mod.F16, P3)
+    assert g.flags_in_effect() & lbm_mod.ROUND_STOCHASTIC
+    with pytest.raises(lbm_mod.LbmError):
+        g.step(1)  # no geometry yet
+    with pytest.raises(lbm_mod.LbmError):
+        g.set_tile(64, 16, 8)
+
+
+def _sphere_samples(wl, n_each=12, seed=3):
+    from scipy.ndimage import binary_dilation
+    rng = np.random.default_rng(seed)
+    fluid = np.argwhere(wl.solid == 0)
+    near = np.argwhere(binary_dilation(wl.solid.astype(bool), iterations=3) & (wl.solid == 0))
+    r1 = wl.rho1
+    iface = np.argwhere((np.abs(np.roll(r1, 1, 0) - r1) > 0.3) & (wl.solid == 0))
+    pick = lambda a: a[rng.choice(len(a), n_each, replace=False)]
+    return np.concatenate([pick(fluid), pick(near), pick(iface)])
+
+
+@pytest.mark.parametrize("storage,tol", [(0, 1e-12), (1, 2e-6)])
+def test_sphere_full_size_sampled_nodes(oracle_mod, lbm_mod, storage, tol):
+    """The 200 x 200 x 280 sphere case in the benchmark's configuration:
+    after 30 steps, sampled nodes (bulk, near the sphere, on the droplet
+    interface) advance one step exactly as the oracle advances their 7^3
+    windows (the update of a node reads nothing beyond distance 3)."""
+    wl = W.sphere_drop(lam=0.38)
+    g = lbm_mod.lattice3d_from_workload(wl, storage)
+    g.step(30)
+    f = g.get_populations()
+    g.step(1)
+    f1 = g.get_populations()
+    for (z, y, x) in _sphere_samples(wl):
+        idx = np.ix_(np.arange(z - 3, z + 4) % wl.nz, np.arange(y - 3, y + 4) % wl.ny, np.arange(x - 3, x + 4) % wl.nx)
+        o = oracle_mod.Oracle3D(7, 7, 7, 0)
+        o.set_geometry(wl.solid[idx])
+        o.set_params(wl.G_c, wl.G_ads, wl.tau)
+        o.set_populations(f[(slice(None), slice(None)) + idx])
+        o.step(1)
+        ref = o.get_populations()[:, :, 3, 3, 3]
+        got = f1[:, :, z, y, x]
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        assert err < tol, (int(z), int(y), int(x), err)
+    m = g.reduce()
+    assert m[8] == 0

@@ -1,8 +1,9 @@
 """Two fused time steps per launch (LBM_SCHED_TWO_STEP) against one step
 per launch: the populations must be bitwise identical, for every storage
 that allows it, with and without stochastic rounding, periodic and walled
-lattices, several tile shapes, odd step counts and fused diagnostics (the
-steps that record diagnostics run alone).  One step per launch is the path
+lattices, several tile shapes (also with the first step's rows pulled
+again at their finish, LBM_SCHED_REPULL), odd step counts and fused
+diagnostics (the steps that record diagnostics run alone).  One step per launch is the path
 the FP64 oracle parity tests pin."""
 import numpy as np
 import pytest
@@ -12,6 +13,7 @@ from paper_2505_22256_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TWO = 8
+REPULL = 16
 
 
 def _cases():
@@ -25,7 +27,8 @@ def _cases():
 @pytest.mark.parametrize("storage,flags", [(1, 0), (2, 0), (2, 1024), (3, 0), (3, 1024)])
 def test_two_step_is_bitwise_one_step(lbm_mod, storage, flags):
     tiles = [(128, 16, TWO), (64, 8, TWO | 2), (128, 0, TWO), (128, 32, TWO | 3), (64, 0, TWO | 4),
-             (256, 24, TWO | 2), (256, 0, TWO)]
+             (256, 24, TWO | 2), (256, 0, TWO), (128, 24, TWO | REPULL | 2), (64, 32, TWO | REPULL | 2),
+             (64, 7, TWO | REPULL | 1), (128, 0, TWO | REPULL)]
     for ci, wl in enumerate(_cases()):
         ref = lbm_mod.lattice_from_workload(wl, storage, flags)
         ref.set_tile(256, 16, 0)
@@ -60,6 +63,14 @@ def test_two_step_with_fused_diagnostics(lbm_mod, steps, every, t_diag):
     assert ta == tb == t_diag
     for q in range(8):
         assert abs(da[q] - db[q]) <= 1e-12 * max(abs(da[q]), 1.0), q
+
+
+def test_repull_needs_two_steps(lbm_mod):
+    g = lbm_mod.Lattice(20, 20, lbm_mod.F32, 3)
+    with pytest.raises(lbm_mod.LbmError):
+        g.set_tile(128, 16, REPULL)
+    g.set_tile(128, 16, TWO | REPULL)
+    assert tuple(g.get_tile()) == (128, 16, TWO | REPULL)
 
 
 def test_two_step_refused_for_fp64(lbm_mod):
