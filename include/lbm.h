@@ -243,6 +243,24 @@ int lbm_get_fields(lbm_ctx *c, double *rho1, double *rho2, double *ux, double *u
  * rho1 are 0.  Synchronous; ESTATE before initialisation. */
 int lbm_reduce(lbm_ctx *c, double out[8]);
 
+/* lbm_reduce for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * eight diagnostics, written to d_out, the caller's device memory (8
+ * doubles, 8-byte aligned), enqueued on the context's stream and not
+ * synchronised (read d_out after lbm_synchronize or a stream wait).  No
+ * device or host allocation and no copy: the workgroup partials go to a
+ * 1 MiB device array that the library holds on each GPU it runs on until
+ * the process ends, so at most 16384 workgroup records: EINVAL for a
+ * lattice that needs more (the pass runs 252-column strips in segments of
+ * the tile's seg_rows rows, 64 when that is 0: ceil(nx / 252) times
+ * ceil(ny / seg_rows), rounded up to a multiple of 8, must not exceed
+ * 16384).  Every call on one GPU uses the same
+ * array: calls that overlap in time on one GPU (other streams, other
+ * contexts, other threads) race and must be serialised by the caller; the
+ * array needs no clearing (every record is written before it is read).
+ * ESTATE before initialisation; EINVAL for a null or misaligned d_out. */
+int lbm_reduce_noalloc(lbm_ctx *c, double *d_out);
+
 /* Static contact angle (degrees, measured through component 1).  Interface
  * points where rho^e = (rho1 - rho2)/(rho1 + rho2) (Eq. 10) changes sign
  * along x- and y-links between fluid nodes, by linear interpolation; points

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -299,11 +300,74 @@ int fields_and_reduce(lbm_ctx *c)
     return LBM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free diagnostics (lbm_reduce_noalloc):
+// the workgroup partials of the reduction pass live in this file-scope
+// array, one copy per device, for the life of the process.  Its host-side
+// name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+constexpr int NOALLOC_MAX_PARTS = 16384;  // workgroup records of 8 doubles: 1 MiB
+static __device__ __align__(256) double scratch[NOALLOC_MAX_PARTS * 8];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[MAX_DEVICES];
+
+// Address of this device's scratch array (looked up once per device, with
+// that device current).
+int scratch_of(lbm_ctx *c, double **out)
+{
+    if (c->device < 0 || c->device >= MAX_DEVICES) return set_err(c, LBM_EDEVICE, "device index %d out of range", c->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        int cur = -1;
+        HIPCHK(c, hipGetDevice(&cur));
+        if (cur != c->device) HIPCHK(c, hipSetDevice(c->device));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != c->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return set_err(c, LBM_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[c->device] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[c->device];
+    return LBM_OK;
+}
+
+// Diagnostics with no field output: sets out[5], out[6] to 0 on a lattice
+// without fluid nodes (as lbm_reduce does on the host).
+static __global__ void k_reduce_no_fluid(double *out)
+{
+    if (threadIdx.x == 0) {
+        out[5] = 0.0;
+        out[6] = 0.0;
+    }
+}
+
 }  // namespace lbm_host
 
 using namespace lbm_host;
 
 extern "C" {
+
+int lbm_reduce_noalloc(lbm_ctx *c, double *d_out)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!d_out || ((uintptr_t)d_out % alignof(double)) != 0)
+        return set_err(c, LBM_EINVAL, "d_out must be an aligned device pointer to 8 doubles");
+    double *parts = nullptr;
+    rc = scratch_of(c, &parts);
+    if (rc) return rc;
+    int nparts = 0;
+    rc = run_pass(c, P_REDUCE, nullptr, nullptr, nullptr, nullptr, &nparts, parts, NOALLOC_MAX_PARTS);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, (const double *)parts, nparts, d_out);
+    if (c->n_fluid == 0) hipLaunchKernelGGL(k_reduce_no_fluid, dim3(1), dim3(64), 0, c->stream, d_out);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
 
 static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags, void *ext_a, void *ext_b,
                       size_t ext_bytes)

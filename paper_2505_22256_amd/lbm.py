@@ -77,6 +77,7 @@ SIGNATURES = {
     "lbm_time": (_L, [_P]),
     "lbm_get_fields": (_I, [_P, _P, _P, _P, _P]),
     "lbm_reduce": (_I, [_P, _P]),
+    "lbm_reduce_noalloc": (_I, [_P, _P]),
     "lbm_contact_angle": (_I, [_P, _I, _P, ctypes.POINTER(_D)]),
     "lbm_get_tables": (_I, [_P, _P, _P, _P, ctypes.POINTER(_I)]),
     "lbm_set_stream": (_I, [_P, _P]),
@@ -332,6 +333,11 @@ class Lattice:
         out = np.empty(8)
         self._c(self._L.lbm_reduce(self.h, _ptr(out)))
         return out
+
+    def reduce_noalloc(self, d_out: int):
+        """lbm_reduce into the caller's device memory d_out (address of 8
+        doubles), asynchronous on the context's stream, allocating nothing."""
+        self._c(self._L.lbm_reduce_noalloc(self.h, _P(int(d_out))))
 
     def contact_angle(self, wall_kind, wall):
         w = np.ascontiguousarray(wall, dtype=np.float64)

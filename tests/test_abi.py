@@ -28,7 +28,7 @@ def test_header_declares_the_boundary():
         assert core in names
     assert len(names) >= 30
     for core in ("lbm3d_create", "lbm3d_set_geometry", "lbm3d_step", "lbm3d_get_fields", "lbm3d_reduce",
-                 "lbm3d_contact_angle"):
+                 "lbm3d_contact_angle", "lbm_reduce_noalloc"):
         assert core in names
 
 
