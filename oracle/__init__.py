@@ -23,6 +23,7 @@ OK, EINVAL, ESTATE, ENOMEM, EUNSTABLE = 0, -1, -2, -3, -5
 PERIODIC_X, PERIODIC_Y = 1, 2
 SCHEME_ORIGINAL, E8_COPY_OFF, WALLPSI_SELF, VEL_LITERAL, FORCE_DENSITY = 4, 8, 16, 32, 64
 INLET, OUTFLOW = 256, 512
+ADH_D2Q9 = 4096  # reading exploration: S(x) with the D2Q9 weights (CPU only)
 
 
 def build(force: bool = True) -> str:

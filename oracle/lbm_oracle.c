@@ -166,7 +166,7 @@ int oracle_create(oracle_ctx **out, int nx, int ny, unsigned flags)
     if (!out) return ORC_EINVAL;
     *out = NULL;
     if (nx < 5 || ny < 5) return ORC_EINVAL;
-    if (flags & ~(127u | ORC_INLET | ORC_OUTFLOW)) return ORC_EINVAL;
+    if (flags & ~(127u | ORC_INLET | ORC_OUTFLOW | ORC_ADH_D2Q9)) return ORC_EINVAL;
     if ((flags & (ORC_INLET | ORC_OUTFLOW)) && (flags & ORC_PERIODIC_X)) return ORC_EINVAL;
     oracle_ctx *c = (oracle_ctx *)calloc(1, sizeof *c);
     if (!c) return ORC_ENOMEM;
@@ -432,6 +432,15 @@ static void adhesion_vector(const oracle_ctx *c, int x, int y, double S[2])
 {
     S[0] = 0.0;
     S[1] = 0.0;
+    if (c->flags & ORC_ADH_D2Q9) {
+        /* the alternative reading: D2Q9 weights over the eight links */
+        for (int i = 1; i < 9; ++i) {
+            double s = solid_switch(c, x + QX[i], y + QY[i]);
+            S[0] += QW[i] * s * QX[i];
+            S[1] += QW[i] * s * QY[i];
+        }
+        return;
+    }
     for (int g = 0; g < 6; ++g)
         for (int h = 0; h < 2; ++h) {
             int n = 4 * g + h, o = n + 2; /* o is the position opposite n */

@@ -50,7 +50,11 @@ enum {
     ORC_VEL_LITERAL = 32,      /* u^eq = sum j / sum rho (Eq. 4-5 literal)  */
     ORC_FORCE_DENSITY = 64,    /* body force = g_k, not rho_k g_k           */
     ORC_INLET = 256,           /* Zou-He velocity inlet at x = 0 (Sec. 3.3) */
-    ORC_OUTFLOW = 512          /* zero-gradient outflow at x = nx - 1       */
+    ORC_OUTFLOW = 512,         /* zero-gradient outflow at x = nx - 1       */
+    /* Reading exploration (CPU only, no device counterpart): S(x) of Eq. 9
+     * with the D2Q9 weights w_i over the eight links, the literal "w_i" of
+     * the printed equation, instead of the E8 stencil. */
+    ORC_ADH_D2Q9 = 4096
 };
 
 typedef struct oracle_ctx oracle_ctx;

@@ -198,3 +198,20 @@ def test_curved_wall_second_layer_is_copied(oracle_mod):
                 assert row[n] == row[cp[n]]
                 copied += 1
     assert copied > 50
+
+
+def test_d2q9_weight_reading_of_the_adhesion_vector(oracle_mod):
+    """The alternative reading of Eq. 9's w_i (D2Q9 weights over the eight
+    links, an exploration flag of the oracle only): on a flat wall below,
+    S = (0, -(1/9 + 2/36)) = (0, -1/6) on the first fluid row and 0 from
+    the second row on."""
+    nx, ny = 9, 8
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[0] = 1
+    o = oracle_mod.Oracle(nx, ny, oracle_mod.PERIODIC_X | oracle_mod.ADH_D2Q9)
+    o.set_geometry(solid)
+    o.set_params(0.9, 0.1, 1.0)
+    o.init_fields(np.full((ny, nx), 0.5), np.full((ny, nx), 0.5))
+    assert np.allclose(o.adhesion_vector(4, 1), [0.0, -1.0 / 6.0], rtol=0, atol=1e-16)
+    for y in (2, 3, 4):
+        assert np.all(o.adhesion_vector(4, y) == 0.0)
