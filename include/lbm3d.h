@@ -122,13 +122,15 @@ int lbm3d_reduce(lbm3d_ctx *c, double out[9]);
  * EUNSTABLE with fewer than 4 points or a failed fit.  Synchronous. */
 int lbm3d_contact_angle(lbm3d_ctx *c, int wall_kind, const double wall[4], double *theta_deg);
 
-/* Tile of the step kernel: the xy tile is bx x by threads (bx in {32, 64},
- * by in {8, 16}, not 64 x 16), of which (bx-4) x (by-4) are finished (a
- * 2-node halo on each side), marching z segments of seg_planes planes
- * (>= 1).  Default 32 x 8, 32 planes.  Results do not depend on the tile
- * (bitwise). */
-int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int seg_planes);
-int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *seg_planes);
+/* Brick of the collide pass: bx x by x bz nodes per workgroup (bx * by
+ * threads, each marching bz planes), one of 32 x 8 x 4 (the default),
+ * 32 x 8 x 8, 64 x 4 x 4 and 32 x 4 x 8; EINVAL otherwise.  Each step runs a
+ * density pass (psi = rho of every node from the pulled populations,
+ * 2 values per node) and then the collide pass, which stages psi of its
+ * brick and a 2-node halo in LDS and pulls the populations of its own
+ * nodes.  Results do not depend on the brick (bitwise). */
+int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int bz);
+int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *bz);
 
 int lbm3d_set_stream(lbm3d_ctx *c, void *hip_stream);
 /* Fluid nodes, and the algorithmic bytes per fluid-node update: 2

@@ -37,7 +37,8 @@ struct lbm3d_ctx {
     double rho0[2] = {0, 0};
     bool have_geom = false, have_params = false, have_fields = false;
     long t = 0;
-    int bx = 32, by = 8, seg = 32;
+    int bx = 32, by = 8, bz = 4;  // collide-pass brick
+    void *d_psi = nullptr;        // density-pass output: psi of both components per node
     std::string err;
 };
 
@@ -87,7 +88,7 @@ int ensure_partials(lbm3d_ctx *c, size_t n)
 }
 
 template <class C>
-KParams3<C> make_params3(const lbm3d_ctx *c, const void *A, void *B, int bx, int by, int seg)
+KParams3<C> make_params3(const lbm3d_ctx *c, const void *A, void *B, int bx, int by, int bz)
 {
     KParams3<C> p;
     std::memset(&p, 0, sizeof p);
@@ -97,10 +98,11 @@ KParams3<C> make_params3(const lbm3d_ctx *c, const void *A, void *B, int bx, int
     p.ny = c->ny;
     p.nz = c->nz;
     p.flags = c->flags;
-    p.tiles_x = (c->nx + (bx - 4) - 1) / (bx - 4);
-    p.tiles_y = (c->ny + (by - 4) - 1) / (by - 4);
-    p.n_segs = (c->nz + seg - 1) / seg;
-    p.n_units = p.tiles_x * p.tiles_y * p.n_segs;
+    p.bricks_x = (c->nx + bx - 1) / bx;
+    p.bricks_y = (c->ny + by - 1) / by;
+    p.bricks_z = (c->nz + bz - 1) / bz;
+    p.n_units = p.bricks_x * p.bricks_y * p.bricks_z;
+    p.psi = (PsiPair<C> *)c->d_psi;
     p.tick = (unsigned)c->t;
     p.N = c->N;
     const double tau = c->tau;
@@ -138,7 +140,8 @@ int run_pass3_t(lbm3d_ctx *c, Pass3 pass, double *fields, int *nparts)
 {
     using C = typename lbm::Traits<S>::C;
     const bool fp = pass == P3_FIELDS_REDUCE;
-    KParams3<C> p = make_params3<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], fp ? 32 : c->bx, fp ? 8 : c->by, c->seg);
+    KParams3<C> p = make_params3<C>(c, c->buf[c->cur], c->buf[c->cur ^ 1], fp ? 32 : c->bx, fp ? 8 : c->by,
+                                    fp ? 4 : c->bz);
     const int grid = ((p.n_units + 7) / 8) * 8;
     if (nparts) *nparts = grid;
     if (pass != P3_STEP) {
@@ -154,7 +157,7 @@ int run_pass3_t(lbm3d_ctx *c, Pass3 pass, double *fields, int *nparts)
         p.out_uz = fields + 4 * c->N;
     }
     const bool sr = (S == lbm::ST_F16 || S == lbm::ST_BF16) && (c->flags & LBM_ROUND_STOCHASTIC);
-    const hipError_t e = launch3<S>(p, pass, c->bx, c->by, sr, c->stream);
+    const hipError_t e = launch3<S>(p, pass, c->bx, c->by, c->bz, sr, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
@@ -173,7 +176,7 @@ template <int S>
 int inverse3_t(lbm3d_ctx *c, const double *fsrc, const double *rho)
 {
     using C = typename lbm::Traits<S>::C;
-    KParams3<C> p = make_params3<C>(c, nullptr, c->buf[c->cur], 32, 8, c->seg);
+    KParams3<C> p = make_params3<C>(c, nullptr, c->buf[c->cur], 32, 8, 4);
     const long long blocks = (c->N + 255) / 256;
     hipLaunchKernelGGL((k_inverse3<S>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, c->d_solid, fsrc, rho);
     HIPCHK3(c, hipGetLastError());
@@ -194,7 +197,7 @@ template <int S>
 int pull_all_t(lbm3d_ctx *c, double *out)
 {
     using C = typename lbm::Traits<S>::C;
-    KParams3<C> p = make_params3<C>(c, c->buf[c->cur], nullptr, 32, 8, c->seg);
+    KParams3<C> p = make_params3<C>(c, c->buf[c->cur], nullptr, 32, 8, 4);
     const long long blocks = (c->N + 255) / 256;
     hipLaunchKernelGGL((k_pull3_all<S>), dim3((unsigned)blocks), dim3(256), 0, c->stream, p, out);
     HIPCHK3(c, hipGetLastError());
@@ -283,8 +286,9 @@ int lbm3d_create(lbm3d_ctx **out, int nx, int ny, int nz, int storage, unsigned 
     }
     c->stream = c->own_stream;
     const size_t bytes = (size_t)N * 38 * esize(storage);
+    const size_t psi_bytes = (size_t)N * 2 * (storage == LBM_F64 ? sizeof(double) : sizeof(float));
     const bool ok = hipMalloc(&c->buf[0], bytes) == hipSuccess && hipMalloc(&c->buf[1], bytes) == hipSuccess &&
-                    hipMalloc(&c->d_solid, (size_t)N) == hipSuccess &&
+                    hipMalloc(&c->d_psi, psi_bytes) == hipSuccess && hipMalloc(&c->d_solid, (size_t)N) == hipSuccess &&
                     hipMalloc(&c->d_out, 32 * sizeof(double)) == hipSuccess;
     if (!ok) {
         lbm3d_destroy(c);
@@ -301,7 +305,7 @@ void lbm3d_destroy(lbm3d_ctx *c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (void *p : {c->buf[0], c->buf[1], (void *)c->d_solid, (void *)c->d_tmp, (void *)c->d_partials,
+    for (void *p : {c->buf[0], c->buf[1], c->d_psi, (void *)c->d_solid, (void *)c->d_tmp, (void *)c->d_partials,
                     (void *)c->d_out, (void *)c->d_cc})
         if (p) (void)hipFree(p);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -539,23 +543,24 @@ int lbm3d_contact_angle(lbm3d_ctx *c, int wall_kind, const double wall[4], doubl
     return LBM_OK;
 }
 
-int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int seg_planes)
+int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int bz)
 {
     if (!c) return LBM_EINVAL;
-    const bool ok = (bx == 32 && (by == 8 || by == 16)) || (bx == 64 && by == 8);
-    if (!ok || seg_planes < 1) return fail(c, LBM_EINVAL, "tile %d x %d x %d not available", bx, by, seg_planes);
+    const bool ok = (bx == 32 && by == 8 && (bz == 4 || bz == 8)) || (bx == 64 && by == 4 && bz == 4) ||
+                    (bx == 32 && by == 4 && bz == 8);
+    if (!ok) return fail(c, LBM_EINVAL, "brick %d x %d x %d not available", bx, by, bz);
     c->bx = bx;
     c->by = by;
-    c->seg = seg_planes;
+    c->bz = bz;
     return LBM_OK;
 }
 
-int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *seg_planes)
+int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *bz)
 {
     if (!c) return LBM_EINVAL;
     if (bx) *bx = c->bx;
     if (by) *by = c->by;
-    if (seg_planes) *seg_planes = c->seg;
+    if (bz) *bz = c->bz;
     return LBM_OK;
 }
 

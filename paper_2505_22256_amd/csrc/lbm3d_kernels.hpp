@@ -14,14 +14,15 @@
 // (z * ny + y) * nx + x, deviations g = f - w_i rho0 for F32/F16/BF16,
 // all-ones sentinels in every slot of a solid node (as in 2-D).
 //
-// Work decomposition: a workgroup of BX x BY threads owns an xy tile of
-// (BX-4) x (BY-4) columns plus a 2-column halo on every side and marches a
-// segment of z planes.  Each iteration pulls plane p (all tile threads),
-// turns it into psi = rho in an LDS ring of 8 planes, and finishes plane
-// p-2 on the interior threads: their populations are pulled again (the
-// second read of the same addresses, served by the caches, keeps the
-// register count low enough for three waves per SIMD), the stencil sums
-// come from the ring (planes p-4 .. p), then forces, collision and store.
+// Two passes per step.  The density pass pulls every node's populations
+// (Eq. 1 streaming with halfway bounce-back) and writes psi = rho of both
+// components (8 B per node in FP32).  The collide pass gives each
+// workgroup a brick of nodes: it stages psi of the brick and a 2-node halo
+// in LDS, pulls the populations of its own nodes only (the halo costs 8 B
+// of psi, not 38 populations), and computes the stencil sums from LDS,
+// the forces, the collision and the store.  Against a fused pass whose
+// halo nodes pull all their populations to get their density, this reads
+// the populations twice per step but never for halo nodes.
 #pragma once
 
 #include "lbm_device.hpp"
@@ -125,7 +126,8 @@ template <class C> struct KParams3 {
     void *B;        // post-collision set at t   (written)
     int nx, ny, nz;
     unsigned flags;
-    int tiles_x, tiles_y, n_segs, n_units;
+    int bricks_x, bricks_y, bricks_z, n_units;
+    PsiPair<C> *psi;  // psi = rho of both components per node (density pass output)
     unsigned tick;
     long long N;
     C omega, half, negGc, Gw1, Gw2, s1, s2, s3, t2, t3, delta;
@@ -288,15 +290,22 @@ __device__ __forceinline__ C local_G3(const KParams3<C> &p, C re)
 // everything else).
 __constant__ Stencil3 c_st3 = make_stencil3();
 
-// Stencil value at (dx, dy, dz) after the wall rules (Sec. 2.4): an
-// unavailable first-layer position reads zero (psi(x) under WALLPSI_SELF),
-// an unavailable second-layer one what its partner m resolves to (zero
-// under E8_COPY_OFF).  `solid` returns the switch s of Eq. 9 there.
-template <int BX, int BY, class C>
-__device__ __forceinline__ PsiPair<C> resolve3(PsiPair<C> (*ring)[BX * BY], int z, int tid, int dx, int dy, int dz,
-                                               int m, PsiPair<C> first, unsigned flags, bool &solid)
+// A brick of BXB x BYB x BZB nodes and its psi tile (2-node halo).
+template <int BXB, int BYB, int BZB> struct Brick {
+    static constexpr int TX = BXB + 4, TY = BYB + 4, TZ = BZB + 4, NT = BXB * BYB;
+    static constexpr int at(int x, int y, int z) { return (z * TY + y) * TX + x; }  // tile coordinates
+};
+
+// Stencil value at offset (dx, dy, dz) from tile index c after the wall
+// rules (Sec. 2.4): an unavailable first-layer position reads zero (psi(x)
+// under WALLPSI_SELF), an unavailable second-layer one what its partner m
+// resolves to (zero under E8_COPY_OFF).  `solid` returns the switch s of
+// Eq. 9 there.
+template <class BR, class C>
+__device__ __forceinline__ PsiPair<C> resolve3(const PsiPair<C> *tile, int c, int dx, int dy, int dz, int m,
+                                               PsiPair<C> first, unsigned flags, bool &solid)
 {
-    const PsiPair<C> v = ring[(z + dz) & 7][tid + dx + dy * BX];
+    const PsiPair<C> v = tile[c + BR::at(dx, dy, dz)];
     solid = lds_sent(v.a);
     if (!solid) return v;
     if (m < 0) return first;
@@ -306,15 +315,15 @@ __device__ __forceinline__ PsiPair<C> resolve3(PsiPair<C> (*ring)[BX * BY], int 
         zero.b = 0;
         return zero;
     }
-    const PsiPair<C> w = ring[(z + c_st3.z[m]) & 7][tid + c_st3.x[m] + c_st3.y[m] * BX];
+    const PsiPair<C> w = tile[c + BR::at(c_st3.x[m], c_st3.y[m], c_st3.z[m])];
     return lds_sent(w.a) ? first : w;
 }
 
 // Cohesion and adhesion sums at a node with unavailable stencil positions,
-// by opposite pairs as in the bulk path.
-template <int BX, int BY, class C>
-__device__ __forceinline__ void near_sums3(PsiPair<C> (*ring)[BX * BY], int z, int tid, C r1, C r2, unsigned flags,
-                                           C (&s1)[3], C (&s2)[3], C (&Sv)[3])
+// by opposite pairs in the order of the bulk path.
+template <class BR, class C>
+__device__ __forceinline__ void near_sums3(const PsiPair<C> *tile, int c, C r1, C r2, unsigned flags, C (&s1)[3],
+                                           C (&s2)[3], C (&Sv)[3])
 {
     PsiPair<C> first;
     first.a = (flags & F3_WALLPSI_SELF) ? r1 : (C)0;
@@ -328,12 +337,12 @@ __device__ __forceinline__ void near_sums3(PsiPair<C> (*ring)[BX * BY], int z, i
     for (int n = 0; n < NS3; n += 2) {
         const int ex = c_st3.x[n], ey = c_st3.y[n], ez = c_st3.z[n];
         bool ua, ub;
-        const PsiPair<C> a = resolve3<BX, BY, C>(ring, z, tid, ex, ey, ez, c_st3.partner[n], first, flags, ua);
-        const PsiPair<C> b = resolve3<BX, BY, C>(ring, z, tid, -ex, -ey, -ez, c_st3.partner[n + 1], first, flags, ub);
+        const PsiPair<C> a = resolve3<BR, C>(tile, c, ex, ey, ez, c_st3.partner[n], first, flags, ua);
+        const PsiPair<C> b = resolve3<BR, C>(tile, c, -ex, -ey, -ez, c_st3.partner[n + 1], first, flags, ub);
         const C w = (C)e8w3(ex * ex + ey * ey + ez * ez);
         const C d1 = a.a - b.a, d2 = a.b - b.b, ds = (C)(int)ua - (C)(int)ub;
-        // the same products and order as the unrolled bulk path (a zero
-        // component adds nothing there and is skipped here)
+        // the same products and order as the unrolled bulk path (w times
+        // +-1 or +-2 is exact, so w e is the bulk path's constant)
         if (ex != 0) { const C wx = w * (C)ex; s1[0] += wx * d1; s2[0] += wx * d2; Sv[0] += wx * ds; }
         if (ey != 0) { const C wy = w * (C)ey; s1[1] += wy * d1; s2[1] += wy * d2; Sv[1] += wy * ds; }
         if (ez != 0) { const C wz = w * (C)ez; s1[2] += wz * d1; s2[2] += wz * d2; Sv[2] += wz * ds; }
@@ -345,21 +354,19 @@ __device__ __forceinline__ void near_sums3(PsiPair<C> (*ring)[BX * BY], int z, i
 #endif
 constexpr int PAIRS_PER_FENCE = LBM3_PAIRS_PER_FENCE;
 
-// Finish node (x, y, z) of an interior column: populations from the
-// re-pull, stencil sums from the psi ring, forces (Eq. 8-11 and the body
-// force), velocity (Eq. 5), BGK + Guo collision (Eq. 1-2, 6-7), outputs.
-template <int S, int BX, int BY, int MODE>
+// Finish node `node` (tile index c): populations from the pull, stencil
+// sums from the psi tile, forces (Eq. 8-11 and the body force), velocity
+// (Eq. 5), BGK + Guo collision (Eq. 1-2, 6-7), outputs.
+template <int S, class BR, int MODE>
 __device__ __forceinline__ void finish3(const KParams3<typename Traits<S>::C> &p, const PopMem3<S> &mr,
                                        const PopMem3<S> &mw, const Axis &ax, const Axis &ay, const Axis &az,
-                                       const Raw3<S> &q, PsiPair<typename Traits<S>::C> (*ring)[BX * BY], int z,
-                                       RedAcc3 &acc)
+                                       const Raw3<S> &q, const PsiPair<typename Traits<S>::C> *tile, int c,
+                                       uint32_t node, RedAcc3 &acc)
 {
     using T = Traits<S>;
     using C = typename T::C;
     using R = typename T::raw_t;
-    const int tid = threadIdx.x;
-    const uint32_t node = ((uint32_t)az.c * (uint32_t)p.ny + (uint32_t)ay.c) * (uint32_t)p.nx + (uint32_t)ax.c;
-    const PsiPair<C> ctr = ring[z & 7][tid];
+    const PsiPair<C> ctr = tile[c];
     if (lds_sent(ctr.a)) {  // solid node
         if (MODE & K3_FIELDS) {
             p.out_rho1[node] = 0.0;
@@ -373,25 +380,25 @@ __device__ __forceinline__ void finish3(const KParams3<typename Traits<S>::C> &p
     C f[2][19];
     C pr1, pr2;
     (void)pull3<S>(p, mr, ax, ay, az, true, q, f, pr1, pr2);
-    const C r1 = ctr.a, r2 = ctr.b;
+    const C r1 = ctr.a, r2 = ctr.b;  // bitwise pr1, pr2: the density pass pulled the same values
 
     // momenta j_k = sum_i f_i e_i (Eq. 4)
     C j[2][3];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        C a = 0, b = 0, c = 0;
+        C a = 0, b = 0, cc = 0;
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
             if (dx3(i) == 1) a += f[k][i];
             if (dx3(i) == -1) a -= f[k][i];
             if (dy3(i) == 1) b += f[k][i];
             if (dy3(i) == -1) b -= f[k][i];
-            if (dz3(i) == 1) c += f[k][i];
-            if (dz3(i) == -1) c -= f[k][i];
+            if (dz3(i) == 1) cc += f[k][i];
+            if (dz3(i) == -1) cc -= f[k][i];
         }
         j[k][0] = a;
         j[k][1] = b;
-        j[k][2] = c;
+        j[k][2] = cc;
     }
 
     // cohesion sums over the 46 opposite pairs; a sentinel turns them into
@@ -402,8 +409,8 @@ __device__ __forceinline__ void finish3(const KParams3<typename Traits<S>::C> &p
         // a compiler-only fence every few pairs keeps the LDS reads of the
         // stencil from all being hoisted at once (register pressure)
         if (n % (2 * PAIRS_PER_FENCE) == 0) asm volatile("" ::: "memory");
-        const PsiPair<C> a = ring[(z + s3z(n)) & 7][tid + s3x(n) + s3y(n) * BX];
-        const PsiPair<C> b = ring[(z + s3z(n + 1)) & 7][tid + s3x(n + 1) + s3y(n + 1) * BX];
+        const PsiPair<C> a = tile[c + BR::at(s3x(n), s3y(n), s3z(n))];
+        const PsiPair<C> b = tile[c + BR::at(s3x(n + 1), s3y(n + 1), s3z(n + 1))];
         const C d1 = a.a - b.a, d2 = a.b - b.b;
         const C wx = (C)(s3w(n) * s3x(n)), wy = (C)(s3w(n) * s3y(n)), wz = (C)(s3w(n) * s3z(n));
         if (s3x(n) != 0) { s1[0] += wx * d1; s2[0] += wx * d2; }
@@ -414,9 +421,8 @@ __device__ __forceinline__ void finish3(const KParams3<typename Traits<S>::C> &p
     const bool near = __builtin_isnan(s1[0] + s1[1] + s1[2] + s2[0] + s2[1] + s2[2]);
     if (near) {
         asm volatile("" ::: "memory");
-        near_sums3<BX, BY, C>(ring, z, tid, r1, r2, p.flags, s1, s2, Sv);
+        near_sums3<BR, C>(tile, c, r1, r2, p.flags, s1, s2, Sv);
     }
-
     // forces: cohesion (Eq. 8) + adhesion (Eq. 9, 11) + body force
     C F[2][3];
 #pragma unroll
@@ -455,9 +461,9 @@ __device__ __forceinline__ void finish3(const KParams3<typename Traits<S>::C> &p
         p.out_uz[node] = (double)u[2];
     }
     if (MODE & K3_REDUCE) {
-        const double d1 = r1, d2 = r2, a = u[0], b = u[1], c = u[2];
+        const double d1 = r1, d2 = r2, a = u[0], b = u[1], w = u[2];
         if (!__builtin_isfinite(d1) || !__builtin_isfinite(d2) || !__builtin_isfinite(a) || !__builtin_isfinite(b) ||
-            !__builtin_isfinite(c)) {
+            !__builtin_isfinite(w)) {
             acc.bad += 1.0;
         } else {
             const double rt = d1 + d2;
@@ -465,8 +471,8 @@ __device__ __forceinline__ void finish3(const KParams3<typename Traits<S>::C> &p
             acc.m2 += d2;
             acc.px += rt * a;
             acc.py += rt * b;
-            acc.pz += rt * c;
-            const double um = __builtin_sqrt(a * a + b * b + c * c);
+            acc.pz += rt * w;
+            const double um = __builtin_sqrt(a * a + b * b + w * w);
             acc.umax = um > acc.umax ? um : acc.umax;
             acc.rmin = d1 < acc.rmin ? d1 : acc.rmin;
             acc.rmax = d1 > acc.rmax ? d1 : acc.rmax;
@@ -580,69 +586,102 @@ __device__ void block_reduce3(const RedAcc3 &acc, double *out)
     }
 }
 
-// One time step (or one field / diagnostic pass).  Grid: 8 * per_xcd
-// workgroups; workgroup b takes unit (b % 8) * per_xcd + b / 8, so each XCD
-// works on a contiguous run of units; units are numbered tile-x fastest,
-// then tile-y, then z-segment, so the units an XCD runs together are
-// neighbouring tiles of one segment (their halos meet in its L2).
-template <int S, int BX, int BY, int MODE>
-__global__ void __launch_bounds__(BX * BY) k_step3(const KParams3<typename Traits<S>::C> p, int per_xcd)
+// Density pass: psi = rho of both components at every node (Eq. 3 on the
+// pulled populations, Eq. 1 streaming with halfway bounce-back), the
+// all-ones sentinel at solid nodes.  One thread per node.
+template <int S>
+__global__ void __launch_bounds__(256) k_density3(const KParams3<typename Traits<S>::C> p)
 {
     using C = typename Traits<S>::C;
-    constexpr int NT = BX * BY;
-    __shared__ PsiPair<C> ring[8][NT];
+    const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (id >= p.N) return;
+    const long long plane = (long long)p.nx * p.ny;
+    const int z = (int)(id / plane), rem = (int)(id - (long long)z * plane);
+    const int y = rem / p.nx, x = rem - y * p.nx;
+    const Axis ax = make_axis(x, p.nx, p.flags & F3_PERIODIC_X);
+    const Axis ay = make_axis(y, p.ny, p.flags & F3_PERIODIC_Y);
+    const Axis az = make_axis(z, p.nz, p.flags & F3_PERIODIC_Z);
+    const PopMem3<S> m = make_mem3<S>(p.A, p.N);
+    Raw3<S> q;
+    issue3<S>(m, p.nx, p.ny, ax, ay, az, true, q);
+    C f[2][19], r1 = 0, r2 = 0;
+    const bool fluid = pull3<S>(p, m, ax, ay, az, true, q, f, r1, r2);
+    PsiPair<C> ps;
+    ps.a = fluid ? r1 : lds_sentinel<C>();
+    ps.b = fluid ? r2 : lds_sentinel<C>();
+    p.psi[id] = ps;
+}
+
+// Collide pass over bricks of BXB x BYB x BZB nodes (one thread per xy
+// column, marching the brick's planes).  Grid: 8 * per_xcd workgroups;
+// workgroup b takes brick (b % 8) * per_xcd + b / 8, so each XCD works on a
+// contiguous run of bricks (numbered x fastest, then y, then z), whose psi
+// halos meet in that XCD's L2.
+template <int S, int BXB, int BYB, int BZB, int MODE>
+__global__ void __launch_bounds__(BXB * BYB) k_collide3(const KParams3<typename Traits<S>::C> p, int per_xcd)
+{
+    using C = typename Traits<S>::C;
+    using BR = Brick<BXB, BYB, BZB>;
+    __shared__ PsiPair<C> tile[BR::TX * BR::TY * BR::TZ];
     const int b = blockIdx.x;
     const int unit = (b & 7) * per_xcd + (b >> 3);
+    const int tid = threadIdx.x;
     RedAcc3 acc;
     if (unit < p.n_units) {
-        const int tx_i = unit % p.tiles_x, rest = unit / p.tiles_x;
-        const int ty_i = rest % p.tiles_y, seg = rest / p.tiles_y;
-        const int x0 = (int)(((long long)tx_i * p.nx) / p.tiles_x), x1 = (int)(((long long)(tx_i + 1) * p.nx) / p.tiles_x);
-        const int y0 = (int)(((long long)ty_i * p.ny) / p.tiles_y), y1 = (int)(((long long)(ty_i + 1) * p.ny) / p.tiles_y);
-        const int z0 = (int)(((long long)seg * p.nz) / p.n_segs), z1 = (int)(((long long)(seg + 1) * p.nz) / p.n_segs);
-        const int tid = threadIdx.x;
-        const int lx = tid % BX, ly = tid / BX;
-        const int wx = x1 - x0, wy = y1 - y0;
-        const bool active = lx < wx + 4 && ly < wy + 4;
-        const bool interior = lx >= 2 && lx < wx + 2 && ly >= 2 && ly < wy + 2;
-        const Axis ax = make_axis(x0 - 2 + lx, p.nx, p.flags & F3_PERIODIC_X);
-        const Axis ay = make_axis(y0 - 2 + ly, p.ny, p.flags & F3_PERIODIC_Y);
-        const bool col_ok = active && ax.ok && ay.ok;
-        const PopMem3<S> mr = make_mem3<S>(p.A, p.N);
-        const PopMem3<S> mw = make_mem3<S>(p.B, p.N);
-        const bool wz = p.flags & F3_PERIODIC_Z;
-
-        Raw3<S> q, qf;
-        for (int pl = z0 - 2; pl <= z1 + 1; ++pl) {
-            const int zf = pl - 2;  // plane finished in this iteration
-            const bool fin = interior && zf >= z0;
-            const Axis az = make_axis_near(pl, p.nz, wz);
-            const Axis azf = make_axis_near(zf, p.nz, wz);
-            // the loads of plane pl, then the re-pull of the node to finish
-            // (its plane's psi is in the ring since two iterations: solid
-            // nodes load nothing); no loads stay in flight across the
-            // finish, which keeps the register count down
-            issue3<S>(mr, p.nx, p.ny, ax, ay, az, col_ok && az.ok, q);
-            if (fin) {
-                const bool solid = lds_sent(ring[zf & 7][tid].a);
-                issue3<S>(mr, p.nx, p.ny, ax, ay, azf, !solid, qf);
+        const int bxi = unit % p.bricks_x, rest = unit / p.bricks_x;
+        const int byi = rest % p.bricks_y, bzi = rest / p.bricks_y;
+        const int x0 = bxi * BXB, y0 = byi * BYB, z0 = bzi * BZB;
+        const bool wx = p.flags & F3_PERIODIC_X, wy = p.flags & F3_PERIODIC_Y, wz = p.flags & F3_PERIODIC_Z;
+        // psi of the brick and its halo (outside a closed face: the sentinel)
+        for (int t = tid; t < BR::TX * BR::TY * BR::TZ; t += BR::NT) {
+            const int lx = t % BR::TX, r = t / BR::TX;
+            const int ly = r % BR::TY, lz = r / BR::TY;
+            // (a brick may be wider than a small periodic lattice: full wrap)
+            const Axis gx = make_axis(x0 - 2 + lx, p.nx, wx);
+            const Axis gy = make_axis(y0 - 2 + ly, p.ny, wy);
+            const Axis gz = make_axis(z0 - 2 + lz, p.nz, wz);
+            PsiPair<C> v;
+            if (gx.ok && gy.ok && gz.ok) {
+                v = p.psi[((long long)gz.c * p.ny + gy.c) * p.nx + gx.c];
+            } else {
+                v.a = lds_sentinel<C>();
+                v.b = lds_sentinel<C>();
             }
-            // plane pl: densities into the ring
+            tile[t] = v;
+        }
+        __syncthreads();
+        const int lx = tid % BXB, ly = tid / BXB;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x < p.nx && y < p.ny) {
+            const PopMem3<S> mr = make_mem3<S>(p.A, p.N);
+            const PopMem3<S> mw = make_mem3<S>(p.B, p.N);
+            const Axis ax = make_axis(x, p.nx, wx);
+            const Axis ay = make_axis(y, p.ny, wy);
+            const int zend = z0 + BZB < p.nz ? z0 + BZB : p.nz;
+            Raw3<S> q;
             {
-                C f[2][19], r1 = 0, r2 = 0;
-                const bool fl = pull3<S>(p, mr, ax, ay, az, col_ok && az.ok, q, f, r1, r2);
-                PsiPair<C> ps;
-                ps.a = fl ? r1 : lds_sentinel<C>();
-                ps.b = fl ? r2 : lds_sentinel<C>();
-                ring[pl & 7][tid] = ps;
+                const Axis az = make_axis(z0, p.nz, wz);
+                const bool solid = lds_sent(tile[BR::at(lx + 2, ly + 2, 2)].a);
+                issue3<S>(mr, p.nx, p.ny, ax, ay, az, !solid, q);
             }
-            __syncthreads();
-            if (fin) finish3<S, BX, BY, MODE>(p, mr, mw, ax, ay, azf, qf, ring, zf, acc);
+            for (int z = z0; z < zend; ++z) {
+                const Axis az = make_axis(z, p.nz, wz);
+                const int c = BR::at(lx + 2, ly + 2, z - z0 + 2);
+                const uint32_t node = ((uint32_t)z * (uint32_t)p.ny + (uint32_t)y) * (uint32_t)p.nx + (uint32_t)x;
+                Raw3<S> cur = q;
+                // the next plane's loads go out before this node is finished
+                if (z + 1 < zend) {
+                    const Axis azn = make_axis(z + 1, p.nz, wz);
+                    const bool solid = lds_sent(tile[c + BR::at(0, 0, 1)].a);
+                    issue3<S>(mr, p.nx, p.ny, ax, ay, azn, !solid, q);
+                }
+                finish3<S, BR, MODE>(p, mr, mw, ax, ay, az, cur, tile, c, node, acc);
+            }
         }
     }
     if (MODE & K3_REDUCE) {
         __syncthreads();
-        block_reduce3<NT>(acc, p.partials + (long long)b * 9);
+        block_reduce3<BXB * BYB>(acc, p.partials + (long long)b * 9);
     }
 }
 

@@ -572,8 +572,9 @@ class Lattice3D:
         self._c(self._L.lbm3d_contact_angle(self.h, wall_kind, _ptr(w), ctypes.byref(th)))
         return th.value
 
-    def set_tile(self, bx, by, seg_planes):
-        self._c(self._L.lbm3d_set_tile(self.h, bx, by, seg_planes))
+    def set_tile(self, bx, by, bz):
+        """Brick of the collide pass (lbm3d_set_tile)."""
+        self._c(self._L.lbm3d_set_tile(self.h, bx, by, bz))
 
     def get_tile(self):
         a, b, c = _I(), _I(), _I()
