@@ -496,7 +496,7 @@ def sphere_drop(args):
     g.set_stream(stream.cuda_stream)
     if args.tile not in ("default", "auto"):
         vals = [int(v) for v in args.tile.split(",")]
-        g.set_tile(vals[0], vals[1], vals[2])
+        g.set_tile(*vals)
     reps = 5
     chunk = [max(1, steps // reps)] * reps
     with torch.cuda.stream(stream):

@@ -122,15 +122,16 @@ int lbm3d_reduce(lbm3d_ctx *c, double out[9]);
  * EUNSTABLE with fewer than 4 points or a failed fit.  Synchronous. */
 int lbm3d_contact_angle(lbm3d_ctx *c, int wall_kind, const double wall[4], double *theta_deg);
 
-/* Brick of the collide pass: bx x by x bz nodes per workgroup (bx * by
- * threads, each marching bz planes), one of 32 x 8 x 4 (the default),
- * 32 x 8 x 8, 64 x 4 x 4 and 32 x 4 x 8; EINVAL otherwise.  Each step runs a
- * density pass (psi = rho of every node from the pulled populations,
- * 2 values per node) and then the collide pass, which stages psi of its
- * brick and a 2-node halo in LDS and pulls the populations of its own
- * nodes.  Results do not depend on the brick (bitwise). */
-int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int bz);
-int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *bz);
+/* Brick of the collide pass: bx x by x bz nodes per workgroup of
+ * bx * by * tz threads (tz threads per column, each finishing every tz-th
+ * plane of it), one of 32 x 8 x 4 with tz 1 (the default), 2 or 4,
+ * 32 x 8 x 8 with tz 2, and 64 x 4 x 4 with tz 2; EINVAL otherwise.  Each
+ * step runs a density pass (psi = rho of every node from the pulled
+ * populations, 2 values per node) and then the collide pass, which stages
+ * psi of its brick and a 2-node halo in LDS and pulls the populations of
+ * its own nodes.  Results do not depend on the brick (bitwise). */
+int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int bz, int tz);
+int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *bz, int *tz);
 
 int lbm3d_set_stream(lbm3d_ctx *c, void *hip_stream);
 /* Fluid nodes, and the algorithmic bytes per fluid-node update: 2

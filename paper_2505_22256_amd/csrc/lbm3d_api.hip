@@ -37,7 +37,7 @@ struct lbm3d_ctx {
     double rho0[2] = {0, 0};
     bool have_geom = false, have_params = false, have_fields = false;
     long t = 0;
-    int bx = 32, by = 8, bz = 4;  // collide-pass brick
+    int bx = 32, by = 8, bz = 4, tz = 1;  // collide-pass brick and threads in z
     void *d_psi = nullptr;        // density-pass output: psi of both components per node
     std::string err;
 };
@@ -157,7 +157,7 @@ int run_pass3_t(lbm3d_ctx *c, Pass3 pass, double *fields, int *nparts)
         p.out_uz = fields + 4 * c->N;
     }
     const bool sr = (S == lbm::ST_F16 || S == lbm::ST_BF16) && (c->flags & LBM_ROUND_STOCHASTIC);
-    const hipError_t e = launch3<S>(p, pass, c->bx, c->by, c->bz, sr, c->stream);
+    const hipError_t e = launch3<S>(p, pass, c->bx, c->by, c->bz, c->tz, sr, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return LBM_OK;
 }
@@ -543,24 +543,26 @@ int lbm3d_contact_angle(lbm3d_ctx *c, int wall_kind, const double wall[4], doubl
     return LBM_OK;
 }
 
-int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int bz)
+int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int bz, int tz)
 {
     if (!c) return LBM_EINVAL;
-    const bool ok = (bx == 32 && by == 8 && (bz == 4 || bz == 8)) || (bx == 64 && by == 4 && bz == 4) ||
-                    (bx == 32 && by == 4 && bz == 8);
-    if (!ok) return fail(c, LBM_EINVAL, "brick %d x %d x %d not available", bx, by, bz);
+    const bool ok = (bx == 32 && by == 8 && bz == 4 && (tz == 1 || tz == 2 || tz == 4)) ||
+                    (bx == 32 && by == 8 && bz == 8 && tz == 2) || (bx == 64 && by == 4 && bz == 4 && tz == 2);
+    if (!ok) return fail(c, LBM_EINVAL, "brick %d x %d x %d with %d threads in z not available", bx, by, bz, tz);
     c->bx = bx;
     c->by = by;
     c->bz = bz;
+    c->tz = tz;
     return LBM_OK;
 }
 
-int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *bz)
+int lbm3d_get_tile(const lbm3d_ctx *c, int *bx, int *by, int *bz, int *tz)
 {
     if (!c) return LBM_EINVAL;
     if (bx) *bx = c->bx;
     if (by) *by = c->by;
     if (bz) *bz = c->bz;
+    if (tz) *tz = c->tz;
     return LBM_OK;
 }
 

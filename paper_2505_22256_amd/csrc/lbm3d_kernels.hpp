@@ -612,16 +612,20 @@ __global__ void __launch_bounds__(256) k_density3(const KParams3<typename Traits
     p.psi[id] = ps;
 }
 
-// Collide pass over bricks of BXB x BYB x BZB nodes (one thread per xy
-// column, marching the brick's planes).  Grid: 8 * per_xcd workgroups;
-// workgroup b takes brick (b % 8) * per_xcd + b / 8, so each XCD works on a
-// contiguous run of bricks (numbered x fastest, then y, then z), whose psi
-// halos meet in that XCD's L2.
-template <int S, int BXB, int BYB, int BZB, int MODE>
-__global__ void __launch_bounds__(BXB * BYB) k_collide3(const KParams3<typename Traits<S>::C> p, int per_xcd)
+// Collide pass over bricks of BXB x BYB x BZB nodes.  The workgroup has
+// BXB x BYB x TZ threads: thread (x, y, t) finishes planes t, t + TZ, ...
+// of its column (TZ = BZB: one node per thread; TZ < BZB: a short march,
+// the next node's loads issued before the current one is finished).
+// Grid: 8 * per_xcd workgroups; workgroup b takes brick (b % 8) * per_xcd
+// + b / 8, so each XCD works on a contiguous run of bricks (numbered x
+// fastest, then y, then z), whose psi halos meet in that XCD's L2.
+template <int S, int BXB, int BYB, int BZB, int TZ, int MODE>
+__global__ void __launch_bounds__(BXB * BYB * TZ) k_collide3(const KParams3<typename Traits<S>::C> p, int per_xcd)
 {
     using C = typename Traits<S>::C;
     using BR = Brick<BXB, BYB, BZB>;
+    constexpr int NTH = BXB * BYB * TZ;
+    static_assert(BZB % TZ == 0, "the brick depth must be a multiple of the threads in z");
     __shared__ PsiPair<C> tile[BR::TX * BR::TY * BR::TZ];
     const int b = blockIdx.x;
     const int unit = (b & 7) * per_xcd + (b >> 3);
@@ -633,7 +637,7 @@ __global__ void __launch_bounds__(BXB * BYB) k_collide3(const KParams3<typename 
         const int x0 = bxi * BXB, y0 = byi * BYB, z0 = bzi * BZB;
         const bool wx = p.flags & F3_PERIODIC_X, wy = p.flags & F3_PERIODIC_Y, wz = p.flags & F3_PERIODIC_Z;
         // psi of the brick and its halo (outside a closed face: the sentinel)
-        for (int t = tid; t < BR::TX * BR::TY * BR::TZ; t += BR::NT) {
+        for (int t = tid; t < BR::TX * BR::TY * BR::TZ; t += NTH) {
             const int lx = t % BR::TX, r = t / BR::TX;
             const int ly = r % BR::TY, lz = r / BR::TY;
             // (a brick may be wider than a small periodic lattice: full wrap)
@@ -650,7 +654,7 @@ __global__ void __launch_bounds__(BXB * BYB) k_collide3(const KParams3<typename 
             tile[t] = v;
         }
         __syncthreads();
-        const int lx = tid % BXB, ly = tid / BXB;
+        const int lx = tid % BXB, ly = (tid / BXB) % BYB, lt = tid / (BXB * BYB);
         const int x = x0 + lx, y = y0 + ly;
         if (x < p.nx && y < p.ny) {
             const PopMem3<S> mr = make_mem3<S>(p.A, p.N);
@@ -658,22 +662,25 @@ __global__ void __launch_bounds__(BXB * BYB) k_collide3(const KParams3<typename 
             const Axis ax = make_axis(x, p.nx, wx);
             const Axis ay = make_axis(y, p.ny, wy);
             const int zend = z0 + BZB < p.nz ? z0 + BZB : p.nz;
+            const int zs = z0 + lt;
             Raw3<S> q;
-            {
-                const Axis az = make_axis(z0, p.nz, wz);
-                const bool solid = lds_sent(tile[BR::at(lx + 2, ly + 2, 2)].a);
+            if (zs < zend) {
+                const Axis az = make_axis(zs, p.nz, wz);
+                const bool solid = lds_sent(tile[BR::at(lx + 2, ly + 2, lt + 2)].a);
                 issue3<S>(mr, p.nx, p.ny, ax, ay, az, !solid, q);
             }
-            for (int z = z0; z < zend; ++z) {
+            for (int z = zs; z < zend; z += TZ) {
                 const Axis az = make_axis(z, p.nz, wz);
                 const int c = BR::at(lx + 2, ly + 2, z - z0 + 2);
                 const uint32_t node = ((uint32_t)z * (uint32_t)p.ny + (uint32_t)y) * (uint32_t)p.nx + (uint32_t)x;
                 Raw3<S> cur = q;
-                // the next plane's loads go out before this node is finished
-                if (z + 1 < zend) {
-                    const Axis azn = make_axis(z + 1, p.nz, wz);
-                    const bool solid = lds_sent(tile[c + BR::at(0, 0, 1)].a);
-                    issue3<S>(mr, p.nx, p.ny, ax, ay, azn, !solid, q);
+                // the next node's loads go out before this one is finished
+                if constexpr (TZ < BZB) {
+                    if (z + TZ < zend) {
+                        const Axis azn = make_axis(z + TZ, p.nz, wz);
+                        const bool solid = lds_sent(tile[c + BR::at(0, 0, TZ)].a);
+                        issue3<S>(mr, p.nx, p.ny, ax, ay, azn, !solid, q);
+                    }
                 }
                 finish3<S, BR, MODE>(p, mr, mw, ax, ay, az, cur, tile, c, node, acc);
             }
@@ -681,7 +688,7 @@ __global__ void __launch_bounds__(BXB * BYB) k_collide3(const KParams3<typename 
     }
     if (MODE & K3_REDUCE) {
         __syncthreads();
-        block_reduce3<BXB * BYB>(acc, p.partials + (long long)b * 9);
+        block_reduce3<NTH>(acc, p.partials + (long long)b * 9);
     }
 }
 

@@ -445,7 +445,8 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     c->solid.assign((size_t)c->N, 0);
     // measured defaults on the 16384 x 2048 channel: FP32 fuses two steps
     // per launch (128-thread strips, 24-row segments in row bands), FP16
-    // too in 64-thread strips of 32-row segments (4 % over one step);
+    // with round-to-nearest too in 64-thread strips of 32-row segments (4 %
+    // over one step);
     // BF16 (issue-bound, slower fused) and FP64 run one step per launch in
     // 16-row segments and row bands, FP64 with 128-byte aligned strips.
     // With open x edges the steps run in the boundary instances (FP32: 220
@@ -456,12 +457,15 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
         c->block = open_x ? 64 : 128;
         c->seg_rows = 24;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
-    } else if (storage == LBM_F16) {
+    } else if (storage == LBM_F16 && !(c->flags & LBM_ROUND_STOCHASTIC)) {
         c->block = 64;
         c->seg_rows = 32;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
     } else {
-        c->block = storage == LBM_BF16 && open_x ? 128 : 256;
+        // F16 with stochastic rounding (its default) runs like BF16: one
+        // step per launch (46.4 GLUPS at (256, 16) against 41.5 fused at
+        // (64, 32), whose rounding words cost registers twice over)
+        c->block = storage != LBM_F64 && open_x ? 128 : 256;
         c->seg_rows = 16;
         c->sched = storage == LBM_F64 ? (SCHED_ALIGN | SCHED_BANDS) : SCHED_BANDS;
     }

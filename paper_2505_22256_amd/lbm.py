@@ -120,8 +120,8 @@ SIGNATURES = {
     "lbm3d_get_fields": (_I, [_P, _P, _P, _P, _P, _P]),
     "lbm3d_reduce": (_I, [_P, _P]),
     "lbm3d_contact_angle": (_I, [_P, _I, _P, ctypes.POINTER(_D)]),
-    "lbm3d_set_tile": (_I, [_P, _I, _I, _I]),
-    "lbm3d_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "lbm3d_set_tile": (_I, [_P, _I, _I, _I, _I]),
+    "lbm3d_get_tile": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "lbm3d_set_stream": (_I, [_P, _P]),
     "lbm3d_fluid_nodes": (_L, [_P]),
     "lbm3d_bytes_per_update": (_I, [_P]),
@@ -572,14 +572,14 @@ class Lattice3D:
         self._c(self._L.lbm3d_contact_angle(self.h, wall_kind, _ptr(w), ctypes.byref(th)))
         return th.value
 
-    def set_tile(self, bx, by, bz):
-        """Brick of the collide pass (lbm3d_set_tile)."""
-        self._c(self._L.lbm3d_set_tile(self.h, bx, by, bz))
+    def set_tile(self, bx, by, bz, tz=1):
+        """Brick of the collide pass and its threads in z (lbm3d_set_tile)."""
+        self._c(self._L.lbm3d_set_tile(self.h, bx, by, bz, tz))
 
     def get_tile(self):
-        a, b, c = _I(), _I(), _I()
-        self._c(self._L.lbm3d_get_tile(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        a, b, c, d = _I(), _I(), _I(), _I()
+        self._c(self._L.lbm3d_get_tile(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
 
     def set_stream(self, stream_handle: Optional[int]):
         self._c(self._L.lbm3d_set_stream(self.h, None if stream_handle is None else _P(stream_handle)))

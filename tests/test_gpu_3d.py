@@ -48,7 +48,7 @@ def test_fp64_random_geometry_random_populations(oracle_mod, lbm_mod, seed, extr
     flags = [P3, W.PERIODIC_X | W.PERIODIC_Z, 0][seed]
     wl = W.random_small3d(100 + seed, nx=14 + seed, ny=11 + 2 * seed, nz=9 + seed, flags=flags)
     f0 = W.random_populations3d(200 + seed, wl)
-    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, extra, f0, [(32, 8, 4), (64, 4, 4), (32, 4, 8)][seed])
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, extra, f0, [(32, 8, 4, 1), (64, 4, 4, 2), (32, 8, 4, 4)][seed])
     o.step(60)
     g.step(60)
     assert g.time == 60
@@ -61,7 +61,7 @@ def test_fp64_one_voxel_solids(oracle_mod, lbm_mod, extra):
     behind one-node walls everywhere (the sign-rule copy)."""
     wl = W.random_small3d(130, nx=13, ny=12, nz=11, speckle=0.2)
     f0 = W.random_populations3d(131, wl, amplitude=0.1)
-    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, extra, f0, (32, 8, 8))
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, extra, f0, (32, 8, 8, 2))
     o.step(40)
     g.step(40)
     ref = o.get_populations()
@@ -73,7 +73,7 @@ def test_fp64_flat_cap_1000_steps(oracle_mod, lbm_mod):
     """Cap on a flat wall, walls top and bottom, 1000 steps, FP64: the
     populations, the fields and the contact angle."""
     wl = W.flat_drop3d(nx=24, ny=22, nz=14, radius=7.0, G_ads=W.g_ads_of_lambda(1.1))
-    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, tile=(64, 4, 4))
+    o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, tile=(64, 4, 4, 2))
     o.step(1000)
     g.step(1000)
     assert _relmax(g.get_populations(), o.get_populations()) < REL64
@@ -88,7 +88,7 @@ def test_multitile_ragged(oracle_mod, lbm_mod):
     wl = W.random_small3d(140, nx=67, ny=29, nz=23, flags=0, n_blobs=6)
     f0 = W.random_populations3d(141, wl)
     ref = None
-    for tile in ((32, 8, 4), (64, 4, 4), (32, 4, 8)):
+    for tile in ((32, 8, 4, 1), (64, 4, 4, 2), (32, 8, 4, 4)):
         o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, pops=f0, tile=tile)
         if ref is None:
             o.step(25)
@@ -100,7 +100,7 @@ def test_multitile_ragged(oracle_mod, lbm_mod):
 def test_tiling_does_not_change_results(lbm_mod):
     wl = W.random_small3d(150, nx=40, ny=33, nz=26, n_blobs=5)
     ref = None
-    for tile in ((32, 8, 4), (32, 8, 8), (64, 4, 4), (32, 4, 8)):
+    for tile in ((32, 8, 4, 1), (32, 8, 4, 2), (32, 8, 4, 4), (32, 8, 8, 2), (64, 4, 4, 2)):
         g = lbm_mod.lattice3d_from_workload(wl, lbm_mod.F32)
         g.set_tile(*tile)
         g.step(30)
@@ -160,6 +160,8 @@ def test_refusals(lbm_mod):
         g.set_tile(64, 16, 8)
     with pytest.raises(lbm_mod.LbmError):
         g.set_tile(32, 8, 5)
+    with pytest.raises(lbm_mod.LbmError):
+        g.set_tile(32, 8, 8, 3)
 
 
 def _sphere_samples(wl, n_each=12, seed=3):
