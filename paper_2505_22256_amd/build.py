@@ -7,6 +7,15 @@ know the feature, which is harmless.  Mixed-precision fused multiply-adds
 multiply-add of the collision) are disabled too: the separate multiply-add
 and conversion run 2 % faster in the FP16 step kernels, and the results
 stay bitwise independent of the tiling.
+
+Every unit is compiled with -ffp-contract=on: a multiply and an add fuse
+into one rounding only where they form one source expression, never across
+statements.  HIP's default fuses anywhere within a basic block, so the
+fusions (and the last bit of FP32 and 16-bit results) depended on how a
+kernel instance happened to be shaped: in the 3-D collide pass the instance
+with one thread per column fused one multiply-add more than the one with
+four, and their FP32 results differed.  Source-defined fusion makes one
+step per launch, two fused steps and every tile round identically.
 """
 from __future__ import annotations
 
@@ -33,7 +42,7 @@ HEADERS = [os.path.join(CSRC, n) for n in ("lbm_device.hpp", "lbm_kernels.hpp", 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Xclang", "-target-feature", "-Xclang", "-fma-mix-insts",
+         "-Xclang", "-target-feature", "-Xclang", "-fma-mix-insts", "-ffp-contract=on",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

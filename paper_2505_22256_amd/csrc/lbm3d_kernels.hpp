@@ -287,8 +287,34 @@ __device__ __forceinline__ C local_G3(const KParams3<C> &p, C re)
 // The stencil again as a table in constant memory, for the near-wall path,
 // which walks it in a loop that is not unrolled (it runs only where a wall
 // is within two nodes, and unrolled it would take twice the registers of
-// everything else).
-__constant__ Stencil3 c_st3 = make_stencil3();
+// everything else).  One 32-bit word per opposite pair (n, n + 1), so that
+// the uniform loop index turns each entry into one scalar load (bytes
+// would take vector loads, and every such wait would also drain the
+// population loads in flight): bits 0-8 the offset e_n (x, y, z, each + 2
+// in 3 bits), bit 9 set for a second-layer position, bits 10-18 its
+// first-layer partner (same coding).  Position n + 1 and its partner are
+// the negations.  The weight W(|e_n|^2) goes beside it.
+struct NearTable3 {
+    uint32_t code[NS3 / 2];
+    double w[NS3 / 2];
+};
+
+constexpr NearTable3 make_near3()
+{
+    NearTable3 t{};
+    for (int q = 0; q < NS3 / 2; ++q) {
+        const int n = 2 * q, x = kS3.x[n], y = kS3.y[n], z = kS3.z[n], m = kS3.partner[n];
+        uint32_t c = (uint32_t)(x + 2) | (uint32_t)(y + 2) << 3 | (uint32_t)(z + 2) << 6;
+        if (m >= 0)
+            c |= 1u << 9 | (uint32_t)(kS3.x[m] + 2) << 10 | (uint32_t)(kS3.y[m] + 2) << 13 |
+                 (uint32_t)(kS3.z[m] + 2) << 16;
+        t.code[q] = c;
+        t.w[q] = e8w3(x * x + y * y + z * z);
+    }
+    return t;
+}
+
+__constant__ NearTable3 c_near3 = make_near3();
 
 // A brick of BXB x BYB x BZB nodes and its psi tile (2-node halo).
 template <int BXB, int BYB, int BZB> struct Brick {
@@ -301,21 +327,21 @@ template <int BXB, int BYB, int BZB> struct Brick {
 // under WALLPSI_SELF), an unavailable second-layer one what its partner m
 // resolves to (zero under E8_COPY_OFF).  `solid` returns the switch s of
 // Eq. 9 there.
-template <class BR, class C>
-__device__ __forceinline__ PsiPair<C> resolve3(const PsiPair<C> *tile, int c, int dx, int dy, int dz, int m,
+template <class C>
+__device__ __forceinline__ PsiPair<C> resolve3(const PsiPair<C> *tile, int c, int off, bool second, int poff,
                                                PsiPair<C> first, unsigned flags, bool &solid)
 {
-    const PsiPair<C> v = tile[c + BR::at(dx, dy, dz)];
+    const PsiPair<C> v = tile[c + off];
     solid = lds_sent(v.a);
     if (!solid) return v;
-    if (m < 0) return first;
+    if (!second) return first;
     if (flags & F3_COPY_OFF) {
         PsiPair<C> zero;
         zero.a = 0;
         zero.b = 0;
         return zero;
     }
-    const PsiPair<C> w = tile[c + BR::at(c_st3.x[m], c_st3.y[m], c_st3.z[m])];
+    const PsiPair<C> w = tile[c + poff];
     return lds_sent(w.a) ? first : w;
 }
 
@@ -334,12 +360,17 @@ __device__ __forceinline__ void near_sums3(const PsiPair<C> *tile, int c, C r1, 
         Sv[d] = 0;
     }
 #pragma unroll 1
-    for (int n = 0; n < NS3; n += 2) {
-        const int ex = c_st3.x[n], ey = c_st3.y[n], ez = c_st3.z[n];
+    for (int q = 0; q < NS3 / 2; ++q) {
+        const uint32_t code = c_near3.code[q];
+        const int ex = (int)(code & 7u) - 2, ey = (int)(code >> 3 & 7u) - 2, ez = (int)(code >> 6 & 7u) - 2;
+        const bool second = (code >> 9) & 1u;
+        // tile offsets are linear in (x, y, z): the opposite's is the negation
+        const int off = BR::at(ex, ey, ez);
+        const int poff = BR::at((int)(code >> 10 & 7u) - 2, (int)(code >> 13 & 7u) - 2, (int)(code >> 16 & 7u) - 2);
         bool ua, ub;
-        const PsiPair<C> a = resolve3<BR, C>(tile, c, ex, ey, ez, c_st3.partner[n], first, flags, ua);
-        const PsiPair<C> b = resolve3<BR, C>(tile, c, -ex, -ey, -ez, c_st3.partner[n + 1], first, flags, ub);
-        const C w = (C)e8w3(ex * ex + ey * ey + ez * ez);
+        const PsiPair<C> a = resolve3<C>(tile, c, off, second, poff, first, flags, ua);
+        const PsiPair<C> b = resolve3<C>(tile, c, -off, second, -poff, first, flags, ub);
+        const C w = (C)c_near3.w[q];
         const C d1 = a.a - b.a, d2 = a.b - b.b, ds = (C)(int)ua - (C)(int)ub;
         // the same products and order as the unrolled bulk path (w times
         // +-1 or +-2 is exact, so w e is the bulk path's constant)
