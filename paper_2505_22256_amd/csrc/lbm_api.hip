@@ -444,27 +444,27 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     }
     c->solid.assign((size_t)c->N, 0);
     // measured defaults on the 16384 x 2048 channel: FP32 fuses two steps
-    // per launch (128-thread strips, 24-row segments in row bands), FP16
-    // with round-to-nearest too in 64-thread strips of 32-row segments (4 %
-    // over one step);
-    // BF16 (issue-bound, slower fused) and FP64 run one step per launch in
-    // 16-row segments and row bands, FP64 with 128-byte aligned strips.
+    // per launch (128-thread strips, 24-row segments in row bands); so do
+    // FP16 and BF16 in 64-thread strips of 32-row segments, their packed
+    // row state keeping three waves per SIMD (with stochastic rounding FP16
+    // 50.5 GLUPS against 47.3 one step per launch at (256, 16), BF16 48.1
+    // against 46.9; FP16 with round-to-nearest 4 % over one step).
+    // BF16 with round-to-nearest and FP64 run one step per launch in 16-row
+    // segments and row bands, FP64 with 128-byte aligned strips.
     // With open x edges the steps run in the boundary instances (FP32: 220
-    // VGPRs against 195), which run best in narrower strips: FP32 64 threads
-    // (2.4 % over 128), BF16 128 (1.6 % over 256)
+    // VGPRs against 195; 16-bit states unpacked), which run best in narrower
+    // strips: FP32 64 threads (2.4 % over 128), BF16 128 (1.6 % over 256)
     const bool open_x = (flags & (LBM_INLET | LBM_OUTFLOW)) != 0;
+    const bool sr = (c->flags & LBM_ROUND_STOCHASTIC) != 0;
     if (storage == LBM_F32) {
         c->block = open_x ? 64 : 128;
         c->seg_rows = 24;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
-    } else if (storage == LBM_F16 && !(c->flags & LBM_ROUND_STOCHASTIC)) {
+    } else if ((storage == LBM_F16 && !sr) || ((storage == LBM_F16 || storage == LBM_BF16) && sr && !open_x)) {
         c->block = 64;
         c->seg_rows = 32;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
     } else {
-        // F16 with stochastic rounding (its default) runs like BF16: one
-        // step per launch (46.4 GLUPS at (256, 16) against 41.5 fused at
-        // (64, 32), whose rounding words cost registers twice over)
         c->block = storage != LBM_F64 && open_x ? 128 : 256;
         c->seg_rows = 16;
         c->sched = storage == LBM_F64 ? (SCHED_ALIGN | SCHED_BANDS) : SCHED_BANDS;

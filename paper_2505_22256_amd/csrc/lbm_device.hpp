@@ -356,10 +356,45 @@ __device__ __forceinline__ Axis make_axis(int v, int n, bool periodic)
     return a;
 }
 
-template <class C> struct RowState {
+// State of a pulled node between its moments and its collision: the
+// populations f_i(x, t) as deviations and the link bits (bit 8: solid or
+// outside; bits 0-7: bounced-back directions).  get(k, i) gives the value;
+// put_raw stores the two components' pulled elements of direction i.
+template <int S, bool PACK = false> struct RowState {
+    using C = typename Traits<S>::C;
+    using R = typename Traits<S>::raw_t;
     C f[2][9];
-    int info;  // bit 8: solid or outside; bits 0-7: bounced-back directions
+    int info;
+    __device__ __forceinline__ C get(int k, int i) const { return f[k][i]; }
+    __device__ __forceinline__ void put_raw(int i, R a, R b)
+    {
+        f[0][i] = Traits<S>::dec(a);
+        f[1][i] = Traits<S>::dec(b);
+    }
 };
+
+// 16-bit storage: the pulled elements as loaded, two to a register
+// (component 1 in the low half), decoded where they are used.  Decoding is
+// exact, so the arithmetic is that of the decoded state, in half the
+// registers (a thread holds two or six row states).  Only for states that
+// hold pulled values alone: sliding-wall and inlet corrections give values
+// a 16-bit element cannot hold, so the boundary kernels keep them decoded.
+template <int S> struct RowState<S, true> {
+    using C = typename Traits<S>::C;
+    using R = typename Traits<S>::raw_t;
+    static_assert(sizeof(R) == 2, "a packed state holds 16-bit elements");
+    uint32_t h[9];
+    int info;
+    __device__ __forceinline__ C get(int k, int i) const
+    {
+        return Traits<S>::dec((R)(k ? h[i] >> 16 : h[i] & 0xffffu));
+    }
+    __device__ __forceinline__ void put_raw(int i, R a, R b) { h[i] = (uint32_t)a | (uint32_t)b << 16; }
+};
+
+// The state type of a kernel: packed for 16-bit storage without boundary code.
+template <int S, bool BND>
+using StateOf = RowState<S, (S == ST_F16 || S == ST_BF16) && !BND>;
 
 // Cohesion sums sum_n W_n e_n Psi_n over the 24 positions, by opposite
 // pairs (n, n+2) in each group of four (Eq. 8 on the E8 stencil).

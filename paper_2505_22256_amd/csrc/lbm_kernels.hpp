@@ -122,7 +122,7 @@ template <int S> struct GlobalReload {
 template <int S, bool BND, class Reload>
 __device__ __forceinline__ void process_node_src(const KParams<typename Traits<S>::C> &p, const Reload &reload,
                                                  const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
-                                                 RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
+                                                 StateOf<S, BND> &st, typename Traits<S>::C &r1,
                                                  typename Traits<S>::C &r2)
 {
     using T = Traits<S>;
@@ -138,10 +138,9 @@ __device__ __forceinline__ void process_node_src(const KParams<typename Traits<S
         bool ok;
         pull_source(i, cx, ry, col, row, ok);
         // a source outside a non-periodic domain reads as the sentinel
-        st.f[0][i] = ok ? T::dec(q.v[0][i]) : T::dec(T::sentinel());
-        st.f[1][i] = ok ? T::dec(q.v[1][i]) : T::dec(T::sentinel());
-        s1 += st.f[0][i];
-        s2 += st.f[1][i];
+        st.put_raw(i, ok ? q.v[0][i] : T::sentinel(), ok ? q.v[1][i] : T::sentinel());
+        s1 += st.get(0, i);
+        s2 += st.get(1, i);
     }
     s1 += p.rho0[0];
     s2 += p.rho0[1];
@@ -159,11 +158,10 @@ __device__ __forceinline__ void process_node_src(const KParams<typename Traits<S
                 pull_source(i, cx, ry, col, row, ok);
                 if (i > 0 && (!ok || T::sent(q.v[0][i]))) {
                     info |= 1 << (i - 1);
-                    st.f[0][i] = T::dec(reload(0, opp(i)));
-                    st.f[1][i] = T::dec(reload(1, opp(i)));
+                    st.put_raw(i, reload(0, opp(i)), reload(1, opp(i)));
                 }
-                s1 += st.f[0][i];
-                s2 += st.f[1][i];
+                s1 += st.get(0, i);
+                s2 += st.get(1, i);
             }
             st.info = info;
             s1 += p.rho0[0];
@@ -251,7 +249,7 @@ __device__ __forceinline__ void process_node_src(const KParams<typename Traits<S
 template <int S, bool BND>
 __device__ __forceinline__ void process_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
                                              const Axis &cx, const Axis &ry, bool valid, const RawRow<S> &q,
-                                             RowState<typename Traits<S>::C> &st, typename Traits<S>::C &r1,
+                                             StateOf<S, BND> &st, typename Traits<S>::C &r1,
                                              typename Traits<S>::C &r2)
 {
     const GlobalReload<S> reload{m, (uint32_t)(ry.c * p.nx + cx.c) * (uint32_t)sizeof(typename Traits<S>::raw_t)};
@@ -263,7 +261,7 @@ template <int S, int BLOCK, int RS, bool BND>
 __device__ __forceinline__ void process_row(const KParams<typename Traits<S>::C> &p, const PopMem<S> &m,
                                             const Axis &cx, bool col_ok, int r, const RawRow<S> &q,
                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
-                                            RowState<typename Traits<S>::C> &st)
+                                            StateOf<S, BND> &st)
 {
     using C = typename Traits<S>::C;
     const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
@@ -385,10 +383,9 @@ __device__ __forceinline__ void wall_sums(PsiPair<C> (*vr)[BLOCK], int y, int ti
 
 // Finish node (x, y) of an interior column: stencil, forces, velocity,
 // collision and the selected outputs.
-template <int S, int BLOCK, int MODE, int RS = 8>
+template <int S, int BLOCK, int MODE, int RS = 8, class St>
 __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C> &p, const PopMem<S> &mw,
-                                            const Axis &cx, int y, int yw,
-                                            const RowState<typename Traits<S>::C> &st,
+                                            const Axis &cx, int y, int yw, const St &st,
                                             PsiPair<typename Traits<S>::C> (*ring)[BLOCK], RedAcc &acc,
                                             FRingMem<S, BLOCK> *fring = nullptr, unsigned dtick = 0,
                                             FPending<S> *pend = nullptr, bool count = true)
@@ -430,22 +427,21 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
 
     // first moments j_k = sum_i f_i e_i (Eq. 4), definition order; the
     // deviation base w_i rho0 has zero first moment
-    const C(&f)[2][9] = st.f;
     C jx[2], jy[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        C ax = f[k][1];
-        ax -= f[k][3];
-        ax += f[k][5];
-        ax -= f[k][6];
-        ax -= f[k][7];
-        ax += f[k][8];
-        C ay = f[k][2];
-        ay -= f[k][4];
-        ay += f[k][5];
-        ay += f[k][6];
-        ay -= f[k][7];
-        ay -= f[k][8];
+        C ax = st.get(k, 1);
+        ax -= st.get(k, 3);
+        ax += st.get(k, 5);
+        ax -= st.get(k, 6);
+        ax -= st.get(k, 7);
+        ax += st.get(k, 8);
+        C ay = st.get(k, 2);
+        ay -= st.get(k, 4);
+        ay += st.get(k, 5);
+        ay += st.get(k, 6);
+        ay -= st.get(k, 7);
+        ay -= st.get(k, 8);
         jx[k] = ax;
         jy[k] = ay;
     }
@@ -571,7 +567,7 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
         const uint32_t voff = (uint32_t)node * (uint32_t)sizeof(R);
         C gs[2][9];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) gs[k][0] = p.omw * f[k][0] + (C)qw(0) * c0[k];
+        for (int k = 0; k < 2; ++k) gs[k][0] = p.omw * st.get(k, 0) + (C)qw(0) * c0[k];
 #pragma unroll
         for (int pair = 0; pair < 4; ++pair) {
             const int i = pair < 2 ? pair + 1 : pair + 3;  // 1, 2, 5, 6; partners 3, 4, 7, 8
@@ -586,8 +582,8 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
                 const C eF = ex == 0 ? (C)ey * Fy[k] : (ey == 0 ? (C)ex * Fx[k] : (C)ex * Fx[k] + (C)ey * Fy[k]);
                 const C E = (c0[k] + c2[k] * eu2) + h9 * eF;
                 const C O = c1[k] * eu + p.cf3 * eF;
-                gs[k][i] = p.omw * f[k][i] + w * (E + O);
-                gs[k][o] = p.omw * f[k][o] + w * (E - O);
+                gs[k][i] = p.omw * st.get(k, i) + w * (E + O);
+                gs[k][o] = p.omw * st.get(k, o) + w * (E - O);
             }
         }
         // encode (with stochastic rounding: one random word per direction,
@@ -717,7 +713,7 @@ __device__ __forceinline__ void process_segment(const KParams<typename Traits<S>
     const bool col_ok = active && cx.ok;
     const int last = y1 + 1;  // last row whose psi is needed
 
-    RowState<C> ra, rb, rc;
+    StateOf<S, BND> ra, rb, rc;
     RawRow<S> q;
     issue_row<S>(p, mr, cx, col_ok, y0 - 2, q);
     process_row<S, BLOCK, 8, BND>(p, mr, cx, col_ok, y0 - 2, q, ring, ra);
@@ -847,7 +843,7 @@ template <int S, int BLOCK, bool BND>
 __device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>::C> &p, FRingMem<S, BLOCK> *fring,
                                                 const Axis &cx, bool col_ok, int r,
                                                 PsiPair<typename Traits<S>::C> (*ring)[BLOCK],
-                                                RowState<typename Traits<S>::C> &st)
+                                                StateOf<S, BND> &st)
 {
     using C = typename Traits<S>::C;
     const Axis ry = make_axis_near(r, p.ny, p.flags & FL_PERIODIC_Y);
@@ -913,10 +909,11 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     const bool wrap_y = p.flags & FL_PERIODIC_Y;
     const bool core_col = tid >= 5 && tid < w + 5;
 
-    RowState<C> a1, b1, c1, a2, b2, c2;
+    using St = StateOf<S, BND>;
+    St a1, b1, c1, a2, b2, c2;
     RawRow<S> q;
     issue_row<S>(p, mr, cx, act1, p_first, q);
-    auto iter = [&](int pp, RowState<C> &s1w, RowState<C> &s1f, RowState<C> &s2w, RowState<C> &s2f) {
+    auto iter = [&](int pp, St &s1w, St &s1f, St &s2w, St &s2f) {
         const bool fin1 = in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2;
         RawRow<S> qf;
         if constexpr (REPULL) {
@@ -930,7 +927,7 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
             const Axis ry = make_axis_near(pp - 2, p.ny, wrap_y);
             const bool core = core_col && pp - 2 >= y0 && pp - 2 < y1;
             if constexpr (REPULL) {
-                RowState<C> st;
+                St st;
                 C r1 = 0, r2 = 0;
                 process_node<S, BND>(p, mr, cx, ry, act1 && ry.ok, qf, st, r1, r2);
                 finish_node<S, BLOCK, M1, TWO_PR>(p, mw, cx, pp - 2, ry.c, st, ring1, acc, fring, 0u, &pend, core);
@@ -1182,7 +1179,7 @@ k_pull_window(const KParams<typename Traits<S>::C> p, int x0, int y0, int w, int
     const PopMem<S> m = make_mem<S>(p.A, p.N);
     RawRow<S> raw;
     issue_node<S>(m, p.nx, cx, ry, true, raw);
-    RowState<C> st;
+    StateOf<S, true> st;
     C r1, r2;
     process_node<S, true>(p, m, cx, ry, true, raw, st, r1, r2);
     const bool solid = st.info & 256;
