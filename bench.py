@@ -372,10 +372,11 @@ def open_channel(args):
     import torch
     storage = STORAGES[args.storage]
     steps = args.steps if args.steps_given else 1000
+    flags = lbm.ROUND_NEAREST if args.nearest else 0
     out = {}
     for name, wl in (("periodic", W.constrictions()), ("open", W.constrictions(open_ends=True))):
         stream = torch.cuda.Stream()
-        lat = lbm.lattice_from_workload(wl, storage)
+        lat = lbm.lattice_from_workload(wl, storage, flags)
         lat.set_stream(stream.cuda_stream)
         if args.tile not in ("default", "auto"):
             vals = [int(v) for v in args.tile.split(",")]
@@ -389,7 +390,7 @@ def open_channel(args):
         lat.close()
         print(f"[open] {name} {out[name]}", file=sys.stderr, flush=True)
     print(json.dumps({"metric": "open vs periodic constriction channel MLUPS",
-                      "workload": f"constrictions 16384x2048, {args.storage} storage, {steps} steps; open: Zou-He "
+                      "workload": f"constrictions 16384x2048, {args.storage} storage{rounding_label(args)}, {steps} steps; open: Zou-He "
                                   "inlet (Poiseuille, peak 0.01) + outflow", "storage": args.storage,
                       "runs": out, "open_over_periodic": round(out["open"]["MLUPS"] / out["periodic"]["MLUPS"], 4)}),
           flush=True)

@@ -294,12 +294,10 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * is persistent scheduling: one work unit per resident workgroup, each
  * taking an equal share of the strip rows.  Default after lbm_create:
  * FP32 block 128 (64 with LBM_INLET or LBM_OUTFLOW), seg_rows 24,
- * LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; FP16 and BF16 (stochastic
- * rounding) and FP16 with LBM_ROUND_NEAREST block 64, seg_rows 32,
- * LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS, except that with LBM_INLET or
- * LBM_OUTFLOW stochastic rounding takes block 128, seg_rows 16,
- * LBM_SCHED_BANDS; BF16 with LBM_ROUND_NEAREST block 256 (128 with
- * LBM_INLET or LBM_OUTFLOW), seg_rows 16, LBM_SCHED_BANDS; FP64 block 256,
+ * LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS; FP16 and BF16 block 64,
+ * seg_rows 32, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS, except that with
+ * LBM_INLET or LBM_OUTFLOW BF16, and FP16 with stochastic rounding (its
+ * default), take block 128, seg_rows 16, LBM_SCHED_BANDS; FP64 block 256,
  * seg_rows 16, LBM_SCHED_ALIGN | LBM_SCHED_BANDS.  Results do not
  * depend on the tile shape (bitwise).  sched bits: LBM_SCHED_ALIGN makes
  * strips a multiple of 128 bytes wide from x = 0, so that stores never

@@ -547,7 +547,7 @@ int lbm3d_set_tile(lbm3d_ctx *c, int bx, int by, int bz, int tz)
 {
     if (!c) return LBM_EINVAL;
     const bool ok = (bx == 32 && by == 8 && bz == 4 && (tz == 1 || tz == 2 || tz == 4)) ||
-                    (bx == 32 && by == 8 && bz == 8 && tz == 2) || (bx == 64 && by == 4 && bz == 4 && tz == 2);
+                    (bx == 32 && by == 8 && bz == 8 && (tz == 1 || tz == 2)) || (bx == 64 && by == 4 && bz == 4 && tz == 2);
     if (!ok) return fail(c, LBM_EINVAL, "brick %d x %d x %d with %d threads in z not available", bx, by, bz, tz);
     c->bx = bx;
     c->by = by;

@@ -559,8 +559,7 @@ __device__ __forceinline__ void finish3(const KParams3<typename Traits<S>::C> &p
             R o0, o1;
             if constexpr (sr) {
                 const uint32_t rw = lbm::xorshift32(rs);
-                o0 = T::enc_sr(gs[0][i], rw);
-                o1 = T::enc_sr(gs[1][i], rw >> 16);
+                T::enc_sr2(gs[0][i], gs[1][i], rw, o0, o1);
             } else {
                 o0 = T::enc(gs[0][i]);
                 o1 = T::enc(gs[1][i]);
@@ -624,14 +623,16 @@ template <int S>
 __global__ void __launch_bounds__(256) k_density3(const KParams3<typename Traits<S>::C> p)
 {
     using C = typename Traits<S>::C;
-    const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (id >= p.N) return;
-    const long long plane = (long long)p.nx * p.ny;
-    const int z = (int)(id / plane), rem = (int)(id - (long long)z * plane);
-    const int y = rem / p.nx, x = rem - y * p.nx;
-    const Axis ax = make_axis(x, p.nx, p.flags & F3_PERIODIC_X);
-    const Axis ay = make_axis(y, p.ny, p.flags & F3_PERIODIC_Y);
-    const Axis az = make_axis(z, p.nz, p.flags & F3_PERIODIC_Z);
+    // 32-bit index arithmetic: a lattice has fewer than 2^31 nodes
+    const uint32_t id = blockIdx.x * 256u + threadIdx.x;
+    if (id >= (uint32_t)p.N) return;
+    const uint32_t plane = (uint32_t)p.nx * (uint32_t)p.ny;
+    const uint32_t zu = id / plane, rem = id - zu * plane, yu = rem / (uint32_t)p.nx;
+    const int z = (int)zu, y = (int)yu, x = (int)(rem - yu * (uint32_t)p.nx);
+    // coordinates inside the lattice: wrapping needs no division
+    const Axis ax = make_axis_near(x, p.nx, p.flags & F3_PERIODIC_X);
+    const Axis ay = make_axis_near(y, p.ny, p.flags & F3_PERIODIC_Y);
+    const Axis az = make_axis_near(z, p.nz, p.flags & F3_PERIODIC_Z);
     const PopMem3<S> m = make_mem3<S>(p.A, p.N);
     Raw3<S> q;
     issue3<S>(m, p.nx, p.ny, ax, ay, az, true, q);
@@ -690,25 +691,26 @@ __global__ void __launch_bounds__(BXB * BYB * TZ) k_collide3(const KParams3<type
         if (x < p.nx && y < p.ny) {
             const PopMem3<S> mr = make_mem3<S>(p.A, p.N);
             const PopMem3<S> mw = make_mem3<S>(p.B, p.N);
-            const Axis ax = make_axis(x, p.nx, wx);
-            const Axis ay = make_axis(y, p.ny, wy);
+            // the thread's own node lies inside the lattice: no division
+            const Axis ax = make_axis_near(x, p.nx, wx);
+            const Axis ay = make_axis_near(y, p.ny, wy);
             const int zend = z0 + BZB < p.nz ? z0 + BZB : p.nz;
             const int zs = z0 + lt;
             Raw3<S> q;
             if (zs < zend) {
-                const Axis az = make_axis(zs, p.nz, wz);
+                const Axis az = make_axis_near(zs, p.nz, wz);
                 const bool solid = lds_sent(tile[BR::at(lx + 2, ly + 2, lt + 2)].a);
                 issue3<S>(mr, p.nx, p.ny, ax, ay, az, !solid, q);
             }
             for (int z = zs; z < zend; z += TZ) {
-                const Axis az = make_axis(z, p.nz, wz);
+                const Axis az = make_axis_near(z, p.nz, wz);
                 const int c = BR::at(lx + 2, ly + 2, z - z0 + 2);
                 const uint32_t node = ((uint32_t)z * (uint32_t)p.ny + (uint32_t)y) * (uint32_t)p.nx + (uint32_t)x;
                 Raw3<S> cur = q;
                 // the next node's loads go out before this one is finished
                 if constexpr (TZ < BZB) {
                     if (z + TZ < zend) {
-                        const Axis azn = make_axis(z + TZ, p.nz, wz);
+                        const Axis azn = make_axis_near(z + TZ, p.nz, wz);
                         const bool solid = lds_sent(tile[c + BR::at(0, 0, TZ)].a);
                         issue3<S>(mr, p.nx, p.ny, ax, ay, azn, !solid, q);
                     }

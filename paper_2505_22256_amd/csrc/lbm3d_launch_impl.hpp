@@ -20,13 +20,14 @@ hipError_t launch3_t(const KParams3<typename lbm::Traits<S>::C> &p, hipStream_t 
 }
 
 // bricks bx x by x bz with tz threads in z: 32 x 8 x 4 x 1 (the default),
-// 32 x 8 x 4 x 2, 32 x 8 x 4 x 4, 32 x 8 x 8 x 2, 64 x 4 x 4 x 2
+// 32 x 8 x 4 x 2, 32 x 8 x 4 x 4, 32 x 8 x 8 x 1, 32 x 8 x 8 x 2, 64 x 4 x 4 x 2
 template <int S, int MODE>
 hipError_t launch3_tile(const KParams3<typename lbm::Traits<S>::C> &p, int bx, int by, int bz, int tz, hipStream_t st)
 {
     if (bx == 32 && by == 8 && bz == 4 && tz == 1) return launch3_t<S, 32, 8, 4, 1, MODE>(p, st);
     if (bx == 32 && by == 8 && bz == 4 && tz == 2) return launch3_t<S, 32, 8, 4, 2, MODE>(p, st);
     if (bx == 32 && by == 8 && bz == 4 && tz == 4) return launch3_t<S, 32, 8, 4, 4, MODE>(p, st);
+    if (bx == 32 && by == 8 && bz == 8 && tz == 1) return launch3_t<S, 32, 8, 8, 1, MODE>(p, st);
     if (bx == 32 && by == 8 && bz == 8 && tz == 2) return launch3_t<S, 32, 8, 8, 2, MODE>(p, st);
     if (bx == 64 && by == 4 && bz == 4 && tz == 2) return launch3_t<S, 64, 4, 4, 2, MODE>(p, st);
     return hipErrorInvalidValue;

@@ -448,19 +448,21 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     // FP16 and BF16 in 64-thread strips of 32-row segments, their packed
     // row state keeping three waves per SIMD (with stochastic rounding FP16
     // 50.5 GLUPS against 47.3 one step per launch at (256, 16), BF16 48.1
-    // against 46.9; FP16 with round-to-nearest 4 % over one step).
-    // BF16 with round-to-nearest and FP64 run one step per launch in 16-row
-    // segments and row bands, FP64 with 128-byte aligned strips.
+    // against 46.9; with round-to-nearest FP16 58.0 against 48.2, BF16 50.5
+    // against 47.4).  FP64 runs one step per launch in 16-row segments and
+    // row bands with 128-byte aligned strips.
     // With open x edges the steps run in the boundary instances (FP32: 220
     // VGPRs against 195; 16-bit states unpacked), which run best in narrower
-    // strips: FP32 64 threads (2.4 % over 128), BF16 128 (1.6 % over 256)
+    // strips: FP32 64 threads (2.4 % over 128); BF16 and FP16 with
+    // stochastic rounding one step in 128 threads (BF16 with round-to-
+    // nearest: 42.8 GLUPS against 39.8 for two fused steps in 64)
     const bool open_x = (flags & (LBM_INLET | LBM_OUTFLOW)) != 0;
     const bool sr = (c->flags & LBM_ROUND_STOCHASTIC) != 0;
     if (storage == LBM_F32) {
         c->block = open_x ? 64 : 128;
         c->seg_rows = 24;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
-    } else if ((storage == LBM_F16 && !sr) || ((storage == LBM_F16 || storage == LBM_BF16) && sr && !open_x)) {
+    } else if ((storage == LBM_F16 || storage == LBM_BF16) && !(open_x && (sr || storage == LBM_BF16))) {
         c->block = 64;
         c->seg_rows = 32;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;

@@ -107,7 +107,11 @@ template <> struct Traits<ST_F64> {
     __device__ static bool sent(raw_t v) { return __double_as_longlong(v) == -1LL; }
     __device__ static C dec(raw_t v) { return v; }
     __device__ static raw_t enc(C g) { return g; }
-    __device__ static raw_t enc_sr(C g, uint32_t) { return g; }
+    __device__ static void enc_sr2(C g0, C g1, uint32_t, raw_t &o0, raw_t &o1)
+    {
+        o0 = g0;
+        o1 = g1;
+    }
     __device__ static raw_t sentinel() { return __longlong_as_double(-1LL); }
 };
 template <> struct Traits<ST_F32> {
@@ -117,7 +121,11 @@ template <> struct Traits<ST_F32> {
     __device__ static bool sent(raw_t v) { return __float_as_uint(v) == 0xffffffffu; }
     __device__ static C dec(raw_t v) { return v; }
     __device__ static raw_t enc(C g) { return g; }
-    __device__ static raw_t enc_sr(C g, uint32_t) { return g; }
+    __device__ static void enc_sr2(C g0, C g1, uint32_t, raw_t &o0, raw_t &o1)
+    {
+        o0 = g0;
+        o1 = g1;
+    }
     __device__ static raw_t sentinel() { return __uint_as_float(0xffffffffu); }
 };
 template <> struct Traits<ST_F16> {
@@ -127,13 +135,22 @@ template <> struct Traits<ST_F16> {
     __device__ static bool sent(raw_t v) { return v == 0xffffu; }
     __device__ static C dec(raw_t v) { return (float)__builtin_bit_cast(_Float16, v); }
     __device__ static raw_t enc(C g) { return __builtin_bit_cast(uint16_t, (_Float16)g); }
-    // Stochastic rounding: add 13 random bits below the FP16 mantissa of the
-    // FP32 value and truncate them; the result is exactly representable for
-    // normal FP16 values, so the conversion no longer rounds.
-    __device__ static raw_t enc_sr(C g, uint32_t r)
+    // Stochastic rounding of both components of one direction from one
+    // 32-bit random word: add 13 random bits below the FP16 mantissa of the
+    // FP32 value and truncate them (component 1 takes bits 0-12 of the
+    // word, component 2 bits 16-28).  gfx950's conversion instruction does
+    // this with the top 13 bits of its random operand, hence the shifts;
+    // for results in FP16's normal range it gives exactly the add-and-
+    // truncate rule (checked on 4 M values), and it also rounds results in
+    // the subnormal range stochastically at their own precision.
+    __device__ static void enc_sr2(C g0, C g1, uint32_t r, raw_t &o0, raw_t &o1)
     {
-        const uint32_t u = (__float_as_uint(g) + (r & 0x1fffu)) & ~0x1fffu;
-        return __builtin_bit_cast(uint16_t, (_Float16)__uint_as_float(u));
+        typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+        const h2_t z = __builtin_bit_cast(h2_t, 0u);
+        const h2_t v0 = __builtin_amdgcn_cvt_sr_f16_f32(z, g0, r << 19, false);
+        const h2_t v1 = __builtin_amdgcn_cvt_sr_f16_f32(z, g1, r << 3, false);
+        o0 = __builtin_bit_cast(uint16_t, v0[0]);
+        o1 = __builtin_bit_cast(uint16_t, v1[0]);
     }
     __device__ static raw_t sentinel() { return 0xffffu; }
 };
@@ -144,12 +161,20 @@ template <> struct Traits<ST_BF16> {
     __device__ static bool sent(raw_t v) { return v == 0xffffu; }
     __device__ static C dec(raw_t v) { return __uint_as_float((uint32_t)v << 16); }
     __device__ static raw_t enc(C g) { return f32_to_bf16_rne(g); }
-    // Stochastic rounding: add 16 random bits below the BF16 mantissa, truncate.
-    __device__ static raw_t enc_sr(C g, uint32_t r)
+    // Stochastic rounding of both components of one direction: add 16
+    // random bits below the BF16 mantissa and truncate (component 1 takes
+    // bits 0-15 of the word, component 2 bits 16-31).  gfx950's conversion
+    // instruction does exactly this with the top 16 bits of its random
+    // operand (checked on 4 M values of every magnitude).
+    __device__ static void enc_sr2(C g0, C g1, uint32_t r, raw_t &o0, raw_t &o1)
     {
-        const uint32_t u = __float_as_uint(g);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
-        return (uint16_t)((u + (r & 0xffffu)) >> 16);
+        // the builtin returns two BF16 values: reinterpret, never convert
+        typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+        const b2_t z = __builtin_bit_cast(b2_t, 0u);
+        const b2_t v0 = __builtin_amdgcn_cvt_sr_bf16_f32(z, g0, r << 16, false);
+        const b2_t v1 = __builtin_amdgcn_cvt_sr_bf16_f32(z, g1, r, false);
+        o0 = __builtin_bit_cast(uint16_t, v0[0]);
+        o1 = __builtin_bit_cast(uint16_t, v1[0]);
     }
     __device__ static raw_t sentinel() { return 0xffffu; }
 };

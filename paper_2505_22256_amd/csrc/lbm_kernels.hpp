@@ -595,8 +595,7 @@ __device__ __forceinline__ void finish_node(const KParams<typename Traits<S>::C>
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const uint32_t rw = xorshift32(rs);
-                out[0][i] = T::enc_sr(gs[0][i], rw);
-                out[1][i] = T::enc_sr(gs[1][i], rw >> 16);
+                T::enc_sr2(gs[0][i], gs[1][i], rw, out[0][i], out[1][i]);
             }
         } else {
 #pragma unroll

@@ -88,7 +88,7 @@ def test_multitile_ragged(oracle_mod, lbm_mod):
     wl = W.random_small3d(140, nx=67, ny=29, nz=23, flags=0, n_blobs=6)
     f0 = W.random_populations3d(141, wl)
     ref = None
-    for tile in ((32, 8, 4, 1), (64, 4, 4, 2), (32, 8, 4, 4)):
+    for tile in ((32, 8, 4, 1), (64, 4, 4, 2), (32, 8, 4, 4), (32, 8, 8, 1)):
         o, g = _pair(oracle_mod, lbm_mod, wl, lbm_mod.F64, pops=f0, tile=tile)
         if ref is None:
             o.step(25)
@@ -100,7 +100,7 @@ def test_multitile_ragged(oracle_mod, lbm_mod):
 def test_tiling_does_not_change_results(lbm_mod):
     wl = W.random_small3d(150, nx=40, ny=33, nz=26, n_blobs=5)
     ref = None
-    for tile in ((32, 8, 4, 1), (32, 8, 4, 2), (32, 8, 4, 4), (32, 8, 8, 2), (64, 4, 4, 2)):
+    for tile in ((32, 8, 4, 1), (32, 8, 4, 2), (32, 8, 4, 4), (32, 8, 8, 1), (32, 8, 8, 2), (64, 4, 4, 2)):
         g = lbm_mod.lattice3d_from_workload(wl, lbm_mod.F32)
         g.set_tile(*tile)
         g.step(30)

@@ -180,17 +180,18 @@ def test_open_flags_refused_where_unsupported(lbm_mod):
 
 
 def test_default_tiles_with_open_edges(lbm_mod):
-    """Measured defaults: with open x edges FP32 takes 64-thread strips and
-    the 16-bit storages with stochastic rounding 128-thread ones with one
-    step per launch; FP16 with round-to-nearest and FP64 keep theirs;
+    """Measured defaults: with open x edges FP32 takes 64-thread strips,
+    BF16 and FP16 with stochastic rounding 128-thread ones with one step per
+    launch; FP16 with round-to-nearest and FP64 keep theirs;
     closed lattices keep the periodic channel's (16-bit: two fused steps in
-    64-thread strips, except BF16 with round-to-nearest)."""
+    64-thread strips)."""
     want = {
         (lbm_mod.F32, OPEN): (64, 24, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
         (lbm_mod.F32, W.PERIODIC_X): (128, 24, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
         (lbm_mod.BF16, OPEN): (128, 16, lbm_mod.SCHED_BANDS),
         (lbm_mod.BF16, W.PERIODIC_X): (64, 32, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
-        (lbm_mod.BF16, W.PERIODIC_X | lbm_mod.ROUND_NEAREST): (256, 16, lbm_mod.SCHED_BANDS),
+        (lbm_mod.BF16, W.PERIODIC_X | lbm_mod.ROUND_NEAREST): (64, 32, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
+        (lbm_mod.BF16, OPEN | lbm_mod.ROUND_NEAREST): (128, 16, lbm_mod.SCHED_BANDS),
         (lbm_mod.F16, OPEN): (128, 16, lbm_mod.SCHED_BANDS),
         (lbm_mod.F16, W.PERIODIC_X): (64, 32, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
         (lbm_mod.F16, OPEN | lbm_mod.ROUND_NEAREST): (64, 32, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
