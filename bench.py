@@ -164,7 +164,8 @@ def precision_check(steps: int = 5000):
 def calibration_batch(args):
     """The 512-run contact-angle calibration batch (seed 22256): square
     lattices of side 128..512, flat or cylinder walls, per-run G_ads and tau,
-    one launch per step over all runs, HIP graph replays, autotuned tile.
+    one launch per step over all runs, HIP graph replays, autotuned tile
+    (or the one --tile names).
     With --full, runs the configured 10000 steps and reports the angles
     (and their difference from the FP64 oracle values stored for the first
     16 runs)."""
@@ -177,7 +178,14 @@ def calibration_batch(args):
     stream = torch.cuda.Stream()
     b = lbm.Batch(runs, storage)
     b.set_stream(stream.cuda_stream)
-    tile = b.autotune(4)
+    if args.tile in ("default", "auto"):
+        tile = b.autotune(4)
+    else:
+        # a fixed tile (block, seg_rows, sched), e.g. to profile one kernel
+        vals = [int(v) for v in args.tile.split(",")]
+        b.set_tile(vals[0], vals[1])
+        b.set_sched(vals[2] if len(vals) > 2 else 0)
+        tile = b.get_tile() + (b.sched,)
     b.use_graph(True, 50)
     n_fluid = b.fluid_nodes
     steps = runs[0].steps if args.full else args.steps
