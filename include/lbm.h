@@ -114,7 +114,10 @@ enum { LBM_WALL_FLAT = 0, LBM_WALL_CYLINDER = 1 };
 
 /* Create a context on the current HIP device.  nx, ny >= 5; storage one of
  * LBM_F64..LBM_BF16; flags a combination of LBM_PERIODIC_X..LBM_ROUND_NEAREST.
- * Allocates two population buffers of 18*nx*ny elements (ping-pong).
+ * Allocates two population buffers of 18*nx*ny elements (ping-pong).  One
+ * component's 9 direction arrays are addressed through one 32-bit buffer
+ * range, so 9*nx*ny elements must span less than 4 GiB (at most about 60 M
+ * nodes in FP64, 119 M in FP32, 238 M in FP16 or BF16); nx*ny <= 2^30.
  * Errors: EINVAL (sizes, storage, flags), ENOMEM, EDEVICE (no gfx950 GPU). */
 int lbm_create(lbm_ctx **out, int nx, int ny, int storage, unsigned flags);
 
