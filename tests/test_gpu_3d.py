@@ -175,12 +175,19 @@ def _sphere_samples(wl, n_each=12, seed=3):
     return np.concatenate([pick(fluid), pick(near), pick(iface)])
 
 
-@pytest.mark.parametrize("storage,tol", [(0, 1e-12), (1, 2e-6)])
+@pytest.mark.parametrize("storage,tol", [(0, 1e-12), (1, 2e-6), (2, 2e-3), (3, 1.6e-2)])
 def test_sphere_full_size_sampled_nodes(oracle_mod, lbm_mod, storage, tol):
     """The 200 x 200 x 280 sphere case in the benchmark's configuration:
     after 30 steps, sampled nodes (bulk, near the sphere, on the droplet
     interface) advance one step exactly as the oracle advances their 7^3
-    windows (the update of a node reads nothing beyond distance 3)."""
+    windows (the update of a node reads nothing beyond distance 3).  The
+    oracle starts from the device's stored populations, so a reduced
+    storage differs only by the rounding of the new ones to it: FP32
+    roundoff; FP16 and BF16 stochastic rounding, below one unit in the last
+    place of the stored deviation (2^-10 and 2^-7 of it), and a deviation
+    f - w rho0 of the dissolved component can reach nearly the node's
+    largest population (rho0 of component 2 is 0.9 here): bounds of twice
+    the unit, relative to that largest population."""
     wl = W.sphere_drop(lam=0.38)
     g = lbm_mod.lattice3d_from_workload(wl, storage)
     g.step(30)
