@@ -124,8 +124,9 @@ int lbm3d_contact_angle(lbm3d_ctx *c, int wall_kind, const double wall[4], doubl
 
 /* Brick of the collide pass: bx x by x bz nodes per workgroup of
  * bx * by * tz threads (tz threads per column, each finishing every tz-th
- * plane of it), one of 32 x 8 x 4 with tz 1 (the default), 2 or 4,
- * 32 x 8 x 8 with tz 1 or 2, and 64 x 4 x 4 with tz 2; EINVAL otherwise.  Each
+ * plane of it), one of 32 x 8 x 4 with tz 1, 2 or 4, 32 x 8 x 8 with tz 1
+ * or 2, and 64 x 4 x 4 with tz 2; EINVAL otherwise.  The default is
+ * 32 x 8 x 4 with tz 2 for FP32 and with tz 1 for the other storages.  Each
  * step runs a density pass (psi = rho of every node from the pulled
  * populations, 2 values per node) and then the collide pass, which stages
  * psi of its brick and a 2-node halo in LDS and pulls the populations of

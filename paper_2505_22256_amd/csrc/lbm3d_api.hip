@@ -274,6 +274,9 @@ int lbm3d_create(lbm3d_ctx **out, int nx, int ny, int nz, int storage, unsigned 
     c->N = N;
     c->storage = storage;
     c->flags = lbm_host::resolve_rounding(flags, storage);
+    // FP32: two threads per column, whose 512-thread workgroups fit two to
+    // a CU at the four waves per SIMD its collide kernel is built for
+    if (storage == LBM_F32) c->tz = 2;
     hipDeviceProp_t prop;
     if (hipGetDevice(&c->device) != hipSuccess || hipGetDeviceProperties(&prop, c->device) != hipSuccess ||
         std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {

@@ -647,12 +647,15 @@ __global__ void __launch_bounds__(256) k_density3(const KParams3<typename Traits
 // Collide pass over bricks of BXB x BYB x BZB nodes.  The workgroup has
 // BXB x BYB x TZ threads: thread (x, y, t) finishes planes t, t + TZ, ...
 // of its column (TZ = BZB: one node per thread; TZ < BZB: a short march,
-// the next node's loads issued before the current one is finished).
+// the next node's loads issued before the current one is finished).  The
+// FP32 stepping instances are held to 128 registers (four waves per SIMD,
+// a few values spilled), which lets two 512-thread workgroups share a CU.
 // Grid: 8 * per_xcd workgroups; workgroup b takes brick (b % 8) * per_xcd
 // + b / 8, so each XCD works on a contiguous run of bricks (numbered x
 // fastest, then y, then z), whose psi halos meet in that XCD's L2.
 template <int S, int BXB, int BYB, int BZB, int TZ, int MODE>
-__global__ void __launch_bounds__(BXB * BYB * TZ) k_collide3(const KParams3<typename Traits<S>::C> p, int per_xcd)
+__global__ void __launch_bounds__(BXB * BYB * TZ)
+__attribute__((amdgpu_waves_per_eu((S == lbm::ST_F32 && !(MODE & K3_REDUCE)) ? 4 : 1))) k_collide3(const KParams3<typename Traits<S>::C> p, int per_xcd)
 {
     using C = typename Traits<S>::C;
     using BR = Brick<BXB, BYB, BZB>;

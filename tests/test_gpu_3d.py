@@ -164,6 +164,15 @@ def test_refusals(lbm_mod):
         g.set_tile(32, 8, 8, 3)
 
 
+def test_default_bricks(lbm_mod):
+    """FP32 steps with two threads per column of the 32 x 8 x 4 brick, the
+    other storages with one."""
+    for storage, tz in ((lbm_mod.F64, 1), (lbm_mod.F32, 2), (lbm_mod.F16, 1), (lbm_mod.BF16, 1)):
+        g = lbm_mod.Lattice3D(9, 9, 9, storage, P3)
+        assert tuple(g.get_tile()) == (32, 8, 4, tz), storage
+        g.close()
+
+
 def _sphere_samples(wl, n_each=12, seed=3):
     from scipy.ndimage import binary_dilation
     rng = np.random.default_rng(seed)
