@@ -145,10 +145,12 @@ template <> struct Traits<ST_F16> {
     // the subnormal range stochastically at their own precision.
     __device__ static void enc_sr2(C g0, C g1, uint32_t r, raw_t &o0, raw_t &o1)
     {
+        // (the instruction keeps the other half of its destination; only the
+        // written half is read, so the value being converted fills the rest
+        // and no register needs clearing)
         typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
-        const h2_t z = __builtin_bit_cast(h2_t, 0u);
-        const h2_t v0 = __builtin_amdgcn_cvt_sr_f16_f32(z, g0, r << 19, false);
-        const h2_t v1 = __builtin_amdgcn_cvt_sr_f16_f32(z, g1, r << 3, false);
+        const h2_t v0 = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(h2_t, g0), g0, r << 19, false);
+        const h2_t v1 = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(h2_t, g1), g1, r << 3, false);
         o0 = __builtin_bit_cast(uint16_t, v0[0]);
         o1 = __builtin_bit_cast(uint16_t, v1[0]);
     }
@@ -170,9 +172,8 @@ template <> struct Traits<ST_BF16> {
     {
         // the builtin returns two BF16 values: reinterpret, never convert
         typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
-        const b2_t z = __builtin_bit_cast(b2_t, 0u);
-        const b2_t v0 = __builtin_amdgcn_cvt_sr_bf16_f32(z, g0, r << 16, false);
-        const b2_t v1 = __builtin_amdgcn_cvt_sr_bf16_f32(z, g1, r, false);
+        const b2_t v0 = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(b2_t, g0), g0, r << 16, false);
+        const b2_t v1 = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(b2_t, g1), g1, r, false);
         o0 = __builtin_bit_cast(uint16_t, v0[0]);
         o1 = __builtin_bit_cast(uint16_t, v1[0]);
     }
