@@ -857,13 +857,19 @@ __device__ __forceinline__ void process_row_lds(const KParams<typename Traits<S>
     ring[ring_slot<TWO_PR>(r)][threadIdx.x] = ps;
 }
 
-// Rows [y0, y1) of a strip, two steps.  Iteration p (three barriers):
+// Rows [y0, y1) of a strip, two steps.  Iteration p (two barriers):
 //   1. step 1 processes row p (pulled from HBM), the loads of row p + 1 go out;
-//   2. step 1 finishes row p - 2: its downward directions go to LDS, the
+//   -- barrier --
+//   2. the held directions of row p - 3 go to LDS; step 2 finishes row
+//      p - 6 into HBM (its psi(t+1) rows p - 8 .. p - 4 are complete);
+//      step 1 finishes row p - 2: its downward directions go to LDS, the
 //      others to registers;
-//   3. step 2 processes row p - 3 (pulled from LDS);
-//   4. the held directions of row p - 2 go to LDS, and step 2 finishes
-//      row p - 5 into HBM.
+//   -- barrier --
+//   3. step 2 processes row p - 3 (pulled from LDS).
+// Each barrier separates every LDS write from the reads of what it
+// replaces: ring slots are rewritten only one iteration after their last
+// reader, and the held group of a row is written between the second-step
+// pull of the row above (previous iteration) and its own (this one).
 // Lanes cover columns x0-5 .. x1+4: step 1 needs psi(t) there and finishes
 // x0-3 .. x1+2; step 2 needs psi(t+1) on x0-2 .. x1+1 and finishes
 // x0 .. x1-1.  Rows: step 1 pulls y0-5 .. y1+4 and finishes y0-3 .. y1+2;
@@ -911,9 +917,11 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
     using St = StateOf<S, BND>;
     St a1, b1, c1, a2, b2, c2;
     RawRow<S> q;
+    FPending<S> pend;  // held group of the row step 1 finished last
     issue_row<S>(p, mr, cx, act1, p_first, q);
-    auto iter = [&](int pp, St &s1w, St &s1f, St &s2w, St &s2f) {
+    auto iter = [&](int pp, St &s1w, St &s1f, St &s2) {
         const bool fin1 = in1 && pp - 2 >= y0 - 3 && pp - 2 <= y1 + 2;
+        const bool held = in1 && pp - 3 >= y0 - 3 && pp - 3 <= y1 + 2;
         RawRow<S> qf;
         if constexpr (REPULL) {
             if (fin1) issue_row<S>(p, mr, cx, act1, pp - 2, qf);
@@ -921,7 +929,19 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
         if (pp <= p_pull_last) process_row<S, BLOCK, TWO_PR, BND>(p, mr, cx, act1, pp, q, ring1, s1w);
         if (pp + 1 <= p_pull_last) issue_row<S>(p, mr, cx, act1, pp + 1, q);
         __syncthreads();
-        FPending<S> pend;
+        if (held) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    fring->h[k][j][tid] = pend.h[k][j];
+                    fring->u[(pp - 3) & 1][k][j][tid] = pend.u[k][j];
+                }
+        }
+        // s2 holds row p - 6 (written three iterations ago) until the pull
+        // of row p - 3 below replaces it
+        if (in2 && pp - 6 >= y0 && pp - 6 < y1)
+            finish_node<S, BLOCK, M2, TWO_PR>(p, mw, cx, pp - 6, pp - 6, s2, ring2, acc, nullptr, 1u);
         if (fin1) {
             const Axis ry = make_axis_near(pp - 2, p.ny, wrap_y);
             const bool core = core_col && pp - 2 >= y0 && pp - 2 < y1;
@@ -935,30 +955,19 @@ __device__ __forceinline__ void process_segment2(const KParams<typename Traits<S
             }
         }
         __syncthreads();
-        if (pp - 3 >= y0 - 2 && pp - 3 <= y1 + 1) process_row_lds<S, BLOCK, BND>(p, fring, cx, act2, pp - 3, ring2, s2w);
-        __syncthreads();
-        if (fin1) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    fring->h[k][j][tid] = pend.h[k][j];
-                    fring->u[(pp - 2) & 1][k][j][tid] = pend.u[k][j];
-                }
-        }
-        if (in2 && pp - 5 >= y0 && pp - 5 < y1)
-            finish_node<S, BLOCK, M2, TWO_PR>(p, mw, cx, pp - 5, pp - 5, s2f, ring2, acc, nullptr, 1u);
+        if (pp - 3 >= y0 - 2 && pp - 3 <= y1 + 1) process_row_lds<S, BLOCK, BND>(p, fring, cx, act2, pp - 3, ring2, s2);
     };
     // state of row r: step 1 in {a1, b1, c1}, step 2 in {a2, b2, c2}, both by
     // (r - p_first) mod 3; iteration p writes rows p (step 1) and p - 3
-    // (step 2) and finishes rows p - 2 and p - 5
+    // (step 2) and finishes rows p - 2 and p - 6; one iteration past the
+    // last pull finishes the last row of step 2
     for (int pp = p_first;;) {
-        iter(pp, a1, b1, a2, b2);
-        if (++pp > p_last) break;
-        iter(pp, b1, c1, b2, c2);
-        if (++pp > p_last) break;
-        iter(pp, c1, a1, c2, a2);
-        if (++pp > p_last) break;
+        iter(pp, a1, b1, a2);
+        if (++pp > p_last + 1) break;
+        iter(pp, b1, c1, b2);
+        if (++pp > p_last + 1) break;
+        iter(pp, c1, a1, c2);
+        if (++pp > p_last + 1) break;
     }
 }
 
