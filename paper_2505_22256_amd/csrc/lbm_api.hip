@@ -449,8 +449,11 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     // row state keeping three waves per SIMD (with stochastic rounding FP16
     // 50.5 GLUPS against 47.3 one step per launch at (256, 16), BF16 48.1
     // against 46.9; with round-to-nearest FP16 58.0 against 48.2, BF16 50.5
-    // against 47.4).  FP64 runs one step per launch in 16-row segments and
-    // row bands with 128-byte aligned strips.
+    // against 47.4).  FP64 fuses two steps too, in 64-thread strips of
+    // 48-row segments at one wave per SIMD (20.9 GLUPS against 12.7 one
+    // step per launch in 256-thread aligned strips of 16 rows); with open
+    // x edges it steps alone in the latter (no FP64 boundary instance of
+    // the fused kernel is built).
     // With open x edges the steps run in the boundary instances (FP32: 220
     // VGPRs against 195; 16-bit states unpacked), which run best in narrower
     // strips: FP32 64 threads (2.4 % over 128); BF16 and FP16 with
@@ -461,6 +464,10 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     if (storage == LBM_F32) {
         c->block = open_x ? 64 : 128;
         c->seg_rows = 24;
+        c->sched = SCHED_TWO_STEP | SCHED_BANDS;
+    } else if (storage == LBM_F64 && !open_x) {
+        c->block = 64;
+        c->seg_rows = 48;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
     } else if ((storage == LBM_F16 || storage == LBM_BF16) && !(open_x && (sr || storage == LBM_BF16))) {
         c->block = 64;
@@ -715,7 +722,7 @@ int lbm_step(lbm_ctx *c, int n)
     int rc = ready(c);
     if (rc) return rc;
     if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
-    const bool two = (c->sched & SCHED_TWO_STEP) && c->storage != LBM_F64;
+    const bool two = (c->sched & SCHED_TWO_STEP) && !(c->storage == LBM_F64 && boundary_steps(c));
     for (int s = 0; s < n; ++s) {
         const bool diag_now = c->diag_every > 0 && c->t % c->diag_every == 0;
         const bool diag_next = c->diag_every > 0 && (c->t + 1) % c->diag_every == 0;
@@ -903,8 +910,10 @@ int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
         return set_err(c, LBM_EINVAL, "block must be 64/128/256, seg_rows >= 0 (0: persistent), sched in 0..31");
     if ((sched & SCHED_REPULL) && !(sched & SCHED_TWO_STEP))
         return set_err(c, LBM_EINVAL, "LBM_SCHED_REPULL needs LBM_SCHED_TWO_STEP");
-    if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64)
-        return set_err(c, LBM_EINVAL, "two fused steps need FP32, FP16 or BF16 storage");
+    if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64 && block == 256)
+        return set_err(c, LBM_EINVAL, "two fused steps in FP64 take block 64 or 128");
+    if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64 && boundary_steps(c))
+        return set_err(c, LBM_EINVAL, "two fused steps in FP64 need closed or periodic x edges and resting walls");
     c->block = block;
     c->seg_rows = seg_rows;
     c->sched = sched;
@@ -943,9 +952,10 @@ int lbm_autotune(lbm_ctx *c, int steps)
     unsigned best_s = cur_s;
     float best_ms = 1e30f;
     // candidate -1 is the incumbent tile; the rest need a 2 % margin to win.
-    // Each block x rows x schedule is tried with one step per launch and,
-    // except in FP64, with two fused steps per launch.
-    const int n_two = c->storage == LBM_F64 ? 1 : 2;
+    // Each block x rows x schedule is tried with one step per launch and
+    // with two fused steps per launch (FP64: 64- and 128-thread strips, and
+    // only without open edges or sliding walls).
+    const int n_two = (c->storage == LBM_F64 && boundary_steps(c)) ? 1 : 2;
     for (int cand = -1; cand < 3 * 10 * 6 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
         int cb = cur_b, cr = cur_r;
         unsigned sc = cur_s;
@@ -956,6 +966,7 @@ int lbm_autotune(lbm_ctx *c, int steps)
             if (rows[ri] == 0 && (sc & SCHED_BANDS)) continue;  // bands need fixed segments
             if ((sc & SCHED_XCD_SLABS) && ri != 0) continue;   // slabs ignore seg_rows
             if (tw) sc |= SCHED_TWO_STEP;
+            if (tw && c->storage == LBM_F64 && blocks[bi] == 256) continue;  // FP64 fuses in 64 or 128 threads
             cb = blocks[bi];
             cr = rows[ri];
         }

@@ -182,9 +182,9 @@ def test_open_flags_refused_where_unsupported(lbm_mod):
 def test_default_tiles_with_open_edges(lbm_mod):
     """Measured defaults: with open x edges FP32 takes 64-thread strips,
     BF16 and FP16 with stochastic rounding 128-thread ones with one step per
-    launch; FP16 with round-to-nearest and FP64 keep theirs;
-    closed lattices keep the periodic channel's (16-bit: two fused steps in
-    64-thread strips)."""
+    launch; FP16 with round-to-nearest keeps its tile and FP64 steps alone
+    in 256-thread aligned strips; closed lattices keep the periodic
+    channel's (16-bit and FP64: two fused steps in 64-thread strips)."""
     want = {
         (lbm_mod.F32, OPEN): (64, 24, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
         (lbm_mod.F32, W.PERIODIC_X): (128, 24, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
@@ -196,6 +196,7 @@ def test_default_tiles_with_open_edges(lbm_mod):
         (lbm_mod.F16, W.PERIODIC_X): (64, 32, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
         (lbm_mod.F16, OPEN | lbm_mod.ROUND_NEAREST): (64, 32, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
         (lbm_mod.F64, OPEN): (256, 16, lbm_mod.SCHED_ALIGN | lbm_mod.SCHED_BANDS),
+        (lbm_mod.F64, W.PERIODIC_X): (64, 48, lbm_mod.SCHED_TWO_STEP | lbm_mod.SCHED_BANDS),
     }
     for (storage, flags), tile in want.items():
         g = lbm_mod.Lattice(40, 20, storage, flags)
