@@ -301,9 +301,7 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * seg_rows 32, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS, except that with
  * LBM_INLET or LBM_OUTFLOW BF16, and FP16 with stochastic rounding (its
  * default), take block 128, seg_rows 16, LBM_SCHED_BANDS; FP64 block 64,
- * seg_rows 48, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS, and with LBM_INLET or
- * LBM_OUTFLOW block 256, seg_rows 16, LBM_SCHED_ALIGN | LBM_SCHED_BANDS.
- * Results do not
+ * seg_rows 48, LBM_SCHED_TWO_STEP | LBM_SCHED_BANDS.  Results do not
  * depend on the tile shape (bitwise).  sched bits: LBM_SCHED_ALIGN makes
  * strips a multiple of 128 bytes wide from x = 0, so that stores never
  * cover part of a cache line shared with another workgroup;
@@ -311,8 +309,7 @@ int lbm_set_stream(lbm_ctx *c, void *hip_stream);
  * first, so concurrent workgroups cover whole rows; LBM_SCHED_XCD_SLABS
  * gives each of the 8 XCDs one contiguous slab of rows, one workgroup per
  * strip marching down it (seg_rows is ignored).  LBM_SCHED_TWO_STEP (FP32,
- * FP16, BF16: any block; FP64: block 64 or 128, without open x edges or
- * sliding walls, EINVAL otherwise; FP64 steps alone while walls slide)
+ * FP16, BF16: any block; FP64: block 64 or 128, EINVAL otherwise)
  * fuses two time steps per launch: the first step's
  * post-collision rows stay in LDS and the second step pulls them from
  * there, so HBM is read and written once per two steps (strips lose 5

@@ -451,9 +451,8 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
     // against 46.9; with round-to-nearest FP16 58.0 against 48.2, BF16 50.5
     // against 47.4).  FP64 fuses two steps too, in 64-thread strips of
     // 48-row segments at one wave per SIMD (20.9 GLUPS against 12.7 one
-    // step per launch in 256-thread aligned strips of 16 rows); with open
-    // x edges it steps alone in the latter (no FP64 boundary instance of
-    // the fused kernel is built).
+    // step per launch in 256-thread aligned strips of 16 rows), with open
+    // x edges as well.
     // With open x edges the steps run in the boundary instances (FP32: 220
     // VGPRs against 195; 16-bit states unpacked), which run best in narrower
     // strips: FP32 64 threads (2.4 % over 128); BF16 and FP16 with
@@ -465,7 +464,7 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
         c->block = open_x ? 64 : 128;
         c->seg_rows = 24;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
-    } else if (storage == LBM_F64 && !open_x) {
+    } else if (storage == LBM_F64) {
         c->block = 64;
         c->seg_rows = 48;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
@@ -473,10 +472,10 @@ static int create_ctx(lbm_ctx **out, int nx, int ny, int storage, unsigned flags
         c->block = 64;
         c->seg_rows = 32;
         c->sched = SCHED_TWO_STEP | SCHED_BANDS;
-    } else {
-        c->block = storage != LBM_F64 && open_x ? 128 : 256;
+    } else {  // FP16 and BF16 with open x edges, one step per launch
+        c->block = 128;
         c->seg_rows = 16;
-        c->sched = storage == LBM_F64 ? (SCHED_ALIGN | SCHED_BANDS) : SCHED_BANDS;
+        c->sched = SCHED_BANDS;
     }
     *out = c;
     return LBM_OK;
@@ -722,7 +721,7 @@ int lbm_step(lbm_ctx *c, int n)
     int rc = ready(c);
     if (rc) return rc;
     if (n < 0) return set_err(c, LBM_EINVAL, "negative step count");
-    const bool two = (c->sched & SCHED_TWO_STEP) && !(c->storage == LBM_F64 && boundary_steps(c));
+    const bool two = (c->sched & SCHED_TWO_STEP) != 0;
     for (int s = 0; s < n; ++s) {
         const bool diag_now = c->diag_every > 0 && c->t % c->diag_every == 0;
         const bool diag_next = c->diag_every > 0 && (c->t + 1) % c->diag_every == 0;
@@ -912,8 +911,6 @@ int lbm_set_tile(lbm_ctx *c, int block, int seg_rows, unsigned sched)
         return set_err(c, LBM_EINVAL, "LBM_SCHED_REPULL needs LBM_SCHED_TWO_STEP");
     if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64 && block == 256)
         return set_err(c, LBM_EINVAL, "two fused steps in FP64 take block 64 or 128");
-    if ((sched & SCHED_TWO_STEP) && c->storage == LBM_F64 && boundary_steps(c))
-        return set_err(c, LBM_EINVAL, "two fused steps in FP64 need closed or periodic x edges and resting walls");
     c->block = block;
     c->seg_rows = seg_rows;
     c->sched = sched;
@@ -953,9 +950,8 @@ int lbm_autotune(lbm_ctx *c, int steps)
     float best_ms = 1e30f;
     // candidate -1 is the incumbent tile; the rest need a 2 % margin to win.
     // Each block x rows x schedule is tried with one step per launch and
-    // with two fused steps per launch (FP64: 64- and 128-thread strips, and
-    // only without open edges or sliding walls).
-    const int n_two = (c->storage == LBM_F64 && boundary_steps(c)) ? 1 : 2;
+    // with two fused steps per launch (FP64: 64- and 128-thread strips).
+    const int n_two = 2;
     for (int cand = -1; cand < 3 * 10 * 6 * n_two && e == hipSuccess && rc == LBM_OK; ++cand) {
         int cb = cur_b, cr = cur_r;
         unsigned sc = cur_s;

@@ -83,15 +83,13 @@ hipError_t launch_pass_b(const KParams<typename Traits<S>::C> &p, Pass pass, int
     case P_STEP2_RED2:
         if constexpr (S == ST_F64) {
             // FP64: one wavefront per SIMD at any block; 64- and 128-thread strips
-            if constexpr (B == 0) {
-                const bool b128 = block == 128;
-                if (pass == P_STEP2)
-                    return b128 ? launch_step2_t<S, 128, M_STORE>(p, st) : launch_step2_t<S, 64, M_STORE>(p, st);
-                if (pass == P_STEP2_RED1)
-                    return b128 ? launch_step2_t<S, 128, M_STORE | R1>(p, st) : launch_step2_t<S, 64, M_STORE | R1>(p, st);
-                return b128 ? launch_step2_t<S, 128, M_STORE | R2>(p, st) : launch_step2_t<S, 64, M_STORE | R2>(p, st);
-            }
-            return hipErrorInvalidValue;
+            const bool b128 = block == 128;
+            if (pass == P_STEP2)
+                return b128 ? launch_step2_t<S, 128, B | M_STORE>(p, st) : launch_step2_t<S, 64, B | M_STORE>(p, st);
+            if (pass == P_STEP2_RED1)
+                return b128 ? launch_step2_t<S, 128, B | M_STORE | R1>(p, st)
+                            : launch_step2_t<S, 64, B | M_STORE | R1>(p, st);
+            return b128 ? launch_step2_t<S, 128, B | M_STORE | R2>(p, st) : launch_step2_t<S, 64, B | M_STORE | R2>(p, st);
         } else {
             return pass == P_STEP2 ? launch_step2_b<S, B | M_STORE>(p, block, st)
                  : pass == P_STEP2_RED1 ? launch_step2_b<S, B | M_STORE | R1>(p, block, st)

@@ -78,25 +78,22 @@ def test_repull_needs_two_steps(lbm_mod):
 
 
 def test_fp64_two_step_limits(lbm_mod):
-    """FP64 fuses two steps in 64- and 128-thread strips, on lattices
-    without open x edges; a 256-thread strip or an open edge is refused."""
-    g = lbm_mod.Lattice(20, 20, lbm_mod.F64, 3)
-    assert tuple(g.get_tile()) == (64, 48, TWO | 2)
-    g.set_tile(128, 16, TWO)
-    g.set_tile(64, 0, TWO)
-    with pytest.raises(lbm_mod.LbmError) as e:
-        g.set_tile(256, 16, TWO)
-    assert e.value.code == lbm_mod.EINVAL
-    h = lbm_mod.Lattice(20, 20, lbm_mod.F64, lbm_mod.INLET | lbm_mod.OUTFLOW)
-    assert tuple(h.get_tile()) == (256, 16, 1 | 2)
-    with pytest.raises(lbm_mod.LbmError):
-        h.set_tile(64, 16, TWO)
+    """FP64 fuses two steps in 64- and 128-thread strips; a 256-thread strip
+    is refused."""
+    for flags in (3, lbm_mod.INLET | lbm_mod.OUTFLOW):
+        g = lbm_mod.Lattice(20, 20, lbm_mod.F64, flags)
+        assert tuple(g.get_tile()) == (64, 48, TWO | 2)
+        g.set_tile(128, 16, TWO)
+        g.set_tile(64, 0, TWO)
+        with pytest.raises(lbm_mod.LbmError) as e:
+            g.set_tile(256, 16, TWO)
+        assert e.value.code == lbm_mod.EINVAL
 
 
-def test_fp64_steps_alone_while_walls_slide(lbm_mod):
-    """An FP64 context with two fused steps whose walls start sliding steps
-    one at a time (no FP64 boundary instance of the fused kernel), with
-    the results of single steps."""
+def test_fp64_two_step_with_walls_starting_to_slide(lbm_mod):
+    """FP64 with two fused steps whose walls start sliding between calls
+    (the steps after that run in the boundary instance of the fused
+    kernel): the results of single steps, bitwise."""
     wl = W.random_small(23, nx=50, ny=30, flags=W.PERIODIC_X, walls=True)
     out = []
     for tile in ((256, 16, 0), (64, 16, TWO | 2)):
